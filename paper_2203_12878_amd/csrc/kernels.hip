@@ -1,0 +1,962 @@
+// gfx950 kernels of libdrf.
+//
+// Evaluation.  One lane per thread id of the checked protocol; all lanes of
+// a wave execute the same leaf-code instruction (the opcode is read with
+// readfirstlane, so dispatch is a scalar branch) and carry per-lane
+// activity for if / for^U (bit stacks of saved activity and conditions).
+// This is rule par of the paper's semantics: every thread runs the leaf
+// independently; lanes that took the other branch simply stay inactive.
+// for^S loops are not interpreted at all: the planner turned them into an
+// odometer over symbolic loop digits with an affine phase map.
+//
+// Conflict detection.  Records are u64: index << 32 | tid << 1 | is_write.
+// Within one phase, sorting records groups equal indices and orders each
+// group by tid.  A group (phase, index) is racy iff some record writes and
+// two distinct tids occur (Definition 1); its least pair (tid_i < tid_j)
+// with a writer is (t0, t1) when the least tid t0 writes, else (t0, w0)
+// with w0 the least writing tid.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace drf {
+
+#define DEV __device__ __forceinline__
+
+DEV uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+DEV uint64_t rfl64(uint64_t x) {
+    return ((uint64_t)rfl((uint32_t)(x >> 32)) << 32) | (uint64_t)rfl((uint32_t)x);
+}
+DEV uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+DEV uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+DEV uint64_t ballot(bool p) { return __ballot(p); }
+DEV uint32_t readlane(uint32_t v, uint32_t l) { return __builtin_amdgcn_readlane(v, l); }
+
+// ------------------------------------------------------------ expressions
+template <typename T, bool WIDE>
+DEV T ovf_add(T a, T b, bool &o) {
+    T r = a + b;
+    if constexpr (WIDE) o |= (r >> 63) != 0;
+    return r;
+}
+template <typename T, bool WIDE>
+DEV T ovf_mul(T a, T b, bool &o) {
+    T r = a * b;
+    if constexpr (WIDE) o |= (__umul64hi(a, b) != 0) || ((r >> 63) != 0);
+    return r;
+}
+
+template <typename T, bool WIDE>
+DEV T eval_expr(const uint32_t *__restrict__ c, uint32_t len, const T *vars, T tid, bool &o) {
+    T st[MAXSTACK];
+    uint32_t sp = 0;
+    uint32_t i = 0;
+    while (i < len) {
+        const uint32_t op = rfl(c[i]);
+        if (op == X_CONST) {
+            T v;
+            if constexpr (WIDE) {
+                v = ((uint64_t)rfl(c[i + 2]) << 32) | (uint64_t)rfl(c[i + 1]);
+                o |= (v >> 63) != 0;
+            } else {
+                v = rfl(c[i + 1]);
+            }
+            st[sp++] = v;
+            i += 3;
+        } else if (op == X_TID) {
+            st[sp++] = tid;
+            i += 1;
+        } else if (op == X_VAR) {
+            st[sp++] = vars[rfl(c[i + 1])];
+            i += 2;
+        } else if (op >= X_ADDC && op <= X_SHRC) {
+            const T k = (T)rfl(c[i + 1]);
+            const T a = st[sp - 1];
+            T r;
+            switch (op) {
+            case X_ADDC: r = ovf_add<T, WIDE>(a, k, o); break;
+            case X_MULC: r = ovf_mul<T, WIDE>(a, k, o); break;
+            case X_DIVC: r = a / k; break;
+            case X_MODC: r = a % k; break;
+            case X_ANDC: r = a & k; break;
+            default: r = a >> k; break;   // X_SHRC
+            }
+            st[sp - 1] = r;
+            i += 2;
+        } else if (op == X_TRUE || op == X_FALSE) {
+            st[sp++] = (op == X_TRUE) ? 1 : 0;
+            i += 1;
+        } else if (op == X_NOT) {
+            st[sp - 1] = st[sp - 1] ? 0 : 1;
+            i += 1;
+        } else {
+            const T b = st[--sp];
+            const T a = st[sp - 1];
+            T r;
+            switch (op) {
+            case X_ADD: r = ovf_add<T, WIDE>(a, b, o); break;
+            case X_MONUS: r = a > b ? a - b : 0; break;
+            case X_MUL: r = ovf_mul<T, WIDE>(a, b, o); break;
+            case X_DIV: r = b ? a / b : 0; break;
+            case X_MOD: r = b ? a % b : a; break;
+            case X_SHL:
+                if constexpr (WIDE) {
+                    if (a == 0) r = 0;
+                    else if (b >= 63) { o = true; r = 0; }
+                    else { r = a << b; o |= ((r >> b) != a) || ((r >> 63) != 0); }
+                } else {
+                    r = b >= 32 ? 0 : a << b;
+                }
+                break;
+            case X_SHR: r = b >= (T)(8 * sizeof(T)) ? 0 : a >> b; break;
+            case X_MIN: r = a < b ? a : b; break;
+            case X_MAX: r = a > b ? a : b; break;
+            case X_LT: r = a < b; break;
+            case X_LE: r = a <= b; break;
+            case X_EQ: r = a == b; break;
+            case X_NE: r = a != b; break;
+            case X_GT: r = a > b; break;
+            case X_GE: r = a >= b; break;
+            case X_AND: r = (a && b) ? 1 : 0; break;
+            default: r = (a || b) ? 1 : 0; break;   // X_OR
+            }
+            st[sp - 1] = r;
+            i += 1;
+        }
+    }
+    return st[0];
+}
+
+// --------------------------------------------------------------- leaf code
+// Runs one unsynchronized leaf for this lane's thread id.  sink.acc(active,
+// index, mode) is called by all lanes of the wave at every access.
+template <typename T, bool WIDE, typename Sink>
+DEV void run_leaf(const uint32_t *__restrict__ code, T *vars, T tid, bool act0, bool &ovf, Sink &sink) {
+    T his[MAXSLOTS];
+    uint32_t msave = 0, mcond = 0;
+    bool act = act0;
+    uint32_t pc = 0;
+    for (;;) {
+        const uint32_t op = rfl(code[pc]);
+        if (op == U_ACC) {
+            const uint32_t mode = rfl(code[pc + 1]);
+            const uint32_t len = rfl(code[pc + 2]);
+            bool o = false;
+            const T v = eval_expr<T, WIDE>(code + pc + 3, len, vars, tid, o);
+            if constexpr (WIDE) {
+                o |= (v >> 32) != 0;
+                ovf |= act && o;
+            }
+            sink.acc(act, (uint32_t)v, mode);
+            pc += 3 + len;
+        } else if (op == U_IF) {
+            const uint32_t len = rfl(code[pc + 1]);
+            bool o = false;
+            const T c = eval_expr<T, WIDE>(code + pc + 2, len, vars, tid, o);
+            if constexpr (WIDE) ovf |= act && o;
+            const bool cv = c != 0;
+            msave = (msave << 1) | (act ? 1u : 0u);
+            mcond = (mcond << 1) | (cv ? 1u : 0u);
+            act = act && cv;
+            pc = __any(act) ? pc + 3 + len : rfl(code[pc + 2 + len]);
+        } else if (op == U_ELSE) {
+            act = (msave & 1u) && !(mcond & 1u);
+            pc = __any(act) ? pc + 2 : rfl(code[pc + 1]);
+        } else if (op == U_ENDIF) {
+            act = (msave & 1u) != 0;
+            msave >>= 1;
+            mcond >>= 1;
+            pc += 1;
+        } else if (op == U_FOR) {
+            const uint32_t slot = rfl(code[pc + 1]);
+            const uint32_t ll = rfl(code[pc + 2]);
+            bool o = false;
+            const T lo = eval_expr<T, WIDE>(code + pc + 3, ll, vars, tid, o);
+            const uint32_t hl = rfl(code[pc + 3 + ll]);
+            const T hi = eval_expr<T, WIDE>(code + pc + 4 + ll, hl, vars, tid, o);
+            if constexpr (WIDE) ovf |= act && o;
+            const uint32_t end_pc = rfl(code[pc + 4 + ll + hl]);
+            vars[slot] = lo;
+            his[slot] = hi;
+            msave = (msave << 1) | (act ? 1u : 0u);
+            act = act && (lo < hi);
+            if (__any(act)) {
+                pc = pc + 5 + ll + hl;
+            } else {
+                act = (msave & 1u) != 0;
+                msave >>= 1;
+                pc = end_pc;
+            }
+        } else if (op == U_ENDFOR) {
+            const uint32_t slot = rfl(code[pc + 1]);
+            const T x = vars[slot] + 1;
+            vars[slot] = x;
+            act = (msave & 1u) && (x < his[slot]);
+            if (__any(act)) {
+                pc = rfl(code[pc + 2]);
+            } else {
+                act = (msave & 1u) != 0;
+                msave >>= 1;
+                pc += 3;
+            }
+        } else {
+            break;   // U_END
+        }
+    }
+}
+
+// --------------------------------------------------- nest iteration state
+// Symbolic for^S loops of a nest as an odometer of digits (loop 0 outermost).
+// The loops are unrolled to MAXLOOPS so the digits stay in registers.
+template <typename T>
+struct Odo {
+    uint32_t nloops;
+    uint64_t digit[MAXLOOPS];
+    uint64_t phase;
+
+    DEV void start(const NestDesc &nd, uint64_t f, T *vars) {
+        nloops = nd.nloops;
+        phase = nd.phase_base;
+        uint64_t rem = f;
+#pragma unroll
+        for (int l = MAXLOOPS - 1; l >= 0; l--) {
+            digit[l] = 0;
+            if (l < (int)nloops) {
+                const uint64_t t = nd.trip[l];
+                const uint64_t d = rem % t;
+                rem /= t;
+                digit[l] = d;
+                vars[nd.slot[l]] = (T)(nd.lo[l] + d);
+                phase += d * nd.stride[l];
+            }
+        }
+    }
+    DEV void next(const NestDesc &nd, T *vars) {
+        bool carry = true;
+#pragma unroll
+        for (int l = MAXLOOPS - 1; l >= 0; l--) {
+            if (carry && l < (int)nloops) {
+                const uint64_t d = digit[l] + 1;
+                phase += nd.stride[l];
+                if (d < nd.trip[l]) {
+                    digit[l] = d;
+                    vars[nd.slot[l]] = (T)(nd.lo[l] + d);
+                    carry = false;
+                } else {
+                    phase -= nd.trip[l] * nd.stride[l];
+                    digit[l] = 0;
+                    vars[nd.slot[l]] = (T)nd.lo[l];
+                }
+            }
+        }
+    }
+};
+
+template <typename T>
+DEV void load_fixed(const NestDesc &nd, const FixedVal *__restrict__ fixed, T *vars) {
+    for (uint32_t i = 0; i < nd.nfixed; i++) {
+        const FixedVal fv = fixed[nd.fixed_off + i];
+        vars[rfl(fv.slot)] = (T)rfl64(fv.value);
+    }
+}
+
+// Phase of iteration f (digits decoded from scratch).
+DEV uint64_t phase_of(const NestDesc &nd, uint64_t f) {
+    uint64_t ph = nd.phase_base, rem = f;
+    for (int l = (int)nd.nloops - 1; l >= 0; l--) {
+        ph += (rem % nd.trip[l]) * nd.stride[l];
+        rem /= nd.trip[l];
+    }
+    return ph;
+}
+
+// First iteration whose phase is >= k (phases are non-decreasing in f).
+DEV uint64_t first_iter_at(const NestDesc &nd, uint64_t k) {
+    uint64_t lo = 0, hi = nd.iters;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (phase_of(nd, mid) < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ============================================================= count pass
+struct CountSink {
+    uint32_t n;   // wave-uniform running count of the current phase
+    DEV void acc(bool act, uint32_t, uint32_t) { n += __builtin_popcountll(ballot(act)); }
+};
+
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(WG) void k_count(const Item *__restrict__ items, const NestDesc *__restrict__ nests,
+                                               const ProtoDesc *__restrict__ protos,
+                                               const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
+                                               unsigned long long *__restrict__ phase_counts,
+                                               uint32_t *__restrict__ item_cnt, uint32_t *__restrict__ proto_ovf) {
+    __shared__ uint32_t lds_cnt[MAXSPAN];
+    const Item it = items[blockIdx.x];
+    const NestDesc &nd = nests[it.nest];
+    const ProtoDesc pd = protos[nd.proto];
+    const uint32_t span = it.span;
+    for (uint32_t i = threadIdx.x; i < span; i += WG) lds_cnt[i] = 0;
+    __syncthreads();
+
+    T vars[MAXSLOTS];
+    for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+    load_fixed<T>(nd, fixed, vars);
+    Odo<T> odo;
+    odo.start(nd, it.f0, vars);
+    const uint32_t tid = it.tid0 + threadIdx.x;
+    const bool act0 = tid < pd.n;
+    const uint32_t *leaf = code + nd.code_off;
+    bool ovf = false;
+    CountSink sink{0};
+    uint64_t cur = odo.phase;
+    for (uint64_t f = it.f0; f < it.f1; f++) {
+        if (odo.phase != cur) {
+            if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
+            sink.n = 0;
+            cur = odo.phase;
+        }
+        T v2[MAXSLOTS];
+        for (int s = 0; s < MAXSLOTS; s++) v2[s] = vars[s];
+        run_leaf<T, WIDE>(leaf, v2, (T)tid, act0, ovf, sink);
+        odo.next(nd, vars);
+    }
+    if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
+    if (ballot(ovf) != 0 && lane_id() == 0) atomicOr(&proto_ovf[nd.proto], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < span; i += WG) {
+        const uint32_t c = lds_cnt[i];
+        item_cnt[it.cnt_off + i] = c;
+        if (c) atomicAdd(&phase_counts[it.k_lo + i], (unsigned long long)c);
+    }
+}
+
+// ============================================================== emit pass
+struct EmitSink {
+    uint32_t *cur;              // LDS cursor of the current phase
+    unsigned long long base;    // record position of this item's share of the phase
+    unsigned long long *recs;
+    unsigned long long cap;     // records the buffer holds
+    uint32_t tid;
+    DEV void acc(bool act, uint32_t idx, uint32_t mode) {
+        const uint64_t m = ballot(act);
+        if (m == 0) return;
+        uint32_t off = 0;
+        if (lane_id() == 0) off = atomicAdd(cur, (uint32_t)__builtin_popcountll(m));
+        off = __shfl(off, 0);
+        const unsigned long long pos = base + off + mbcnt(m);
+        if (act && pos < cap) recs[pos] = ((unsigned long long)idx << 32) | ((unsigned long long)tid << 1) | mode;
+    }
+};
+
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, const NestDesc *__restrict__ nests,
+                                              const ProtoDesc *__restrict__ protos,
+                                              const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
+                                              const uint32_t *__restrict__ item_cnt,
+                                              const unsigned long long *__restrict__ big_base,
+                                              unsigned long long *__restrict__ cursor, uint64_t win_lo,
+                                              uint64_t win_n, unsigned long long *__restrict__ recs,
+                                              unsigned long long cap) {
+    __shared__ unsigned long long lds_base[MAXSPAN];
+    __shared__ uint32_t lds_cur[MAXSPAN];
+    const Item it = items[blockIdx.x];
+    const NestDesc &nd = nests[it.nest];
+    const ProtoDesc pd = protos[nd.proto];
+    const uint32_t span = it.span;
+    for (uint32_t i = threadIdx.x; i < span; i += WG) {
+        const uint64_t k = it.k_lo + i;
+        const uint32_t c = item_cnt[it.cnt_off + i];
+        unsigned long long v = ~0ull;
+        if (c && k >= win_lo && k - win_lo < win_n) {
+            const unsigned long long b = big_base[k - win_lo];
+            if (b != ~0ull) v = b + atomicAdd(&cursor[k - win_lo], (unsigned long long)c);
+        }
+        lds_base[i] = v;
+        lds_cur[i] = 0;
+    }
+    __syncthreads();
+
+    T vars[MAXSLOTS];
+    for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+    load_fixed<T>(nd, fixed, vars);
+    Odo<T> odo;
+    odo.start(nd, it.f0, vars);
+    const uint32_t tid = it.tid0 + threadIdx.x;
+    const bool act0 = tid < pd.n;
+    const uint32_t *leaf = code + nd.code_off;
+    bool ovf = false;
+    EmitSink sink{nullptr, 0, recs, cap, tid};
+    for (uint64_t f = it.f0; f < it.f1; f++) {
+        const uint32_t i = (uint32_t)(odo.phase - it.k_lo);
+        const unsigned long long b = lds_base[i];
+        if (b != ~0ull) {
+            sink.cur = &lds_cur[i];
+            sink.base = b;
+            T v2[MAXSLOTS];
+            for (int s = 0; s < MAXSLOTS; s++) v2[s] = vars[s];
+            run_leaf<T, WIDE>(leaf, v2, (T)tid, act0, ovf, sink);
+        }
+        odo.next(nd, vars);
+    }
+}
+
+// ======================================================= LDS sort + scan
+// Bitonic sort of n (power of two) u64 keys in LDS by the whole workgroup.
+DEV void lds_bitonic(unsigned long long *a, uint32_t n) {
+    for (uint32_t size = 2; size <= n; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+                const uint32_t lo = 2 * i - (i & (stride - 1));
+                const uint32_t hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const unsigned long long x = a[lo], y = a[hi];
+                if ((x > y) == asc) { a[lo] = y; a[hi] = x; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+DEV uint32_t rec_idx(unsigned long long r) { return (uint32_t)(r >> 32); }
+DEV uint32_t rec_tid(unsigned long long r) { return (uint32_t)(r >> 1) & 0x7FFFFFFFu; }
+
+// Run state of the segmented conflict scan (all wave-uniform).
+struct RunState {
+    bool open;
+    uint32_t idx, t0, t1, wf;
+    bool t0w, in_t0;
+};
+
+DEV uint64_t bits_from(uint32_t s) { return s >= 64 ? 0ull : (~0ull << s); }
+DEV uint64_t bits_range(uint32_t s, uint32_t e) { return bits_from(s) & ~bits_from(e); }
+
+// Folds lanes [s, e) of the current chunk into the open run.
+DEV void run_segment(RunState &st, uint32_t s, uint32_t e, uint64_t G, uint64_t Wm, uint32_t tidv) {
+    uint64_t seg = bits_range(s, e);
+    uint64_t rest = seg;
+    if (st.in_t0) {
+        const uint64_t g = G & seg;
+        if (g) {
+            const uint32_t gb = (uint32_t)__builtin_ctzll(g);
+            st.t0w = st.t0w || ((Wm & bits_range(s, gb)) != 0);
+            st.in_t0 = false;
+            st.t1 = readlane(tidv, gb);
+            rest = bits_range(gb, e);
+        } else {
+            st.t0w = st.t0w || ((Wm & seg) != 0);
+            rest = 0;
+        }
+    }
+    if (!st.in_t0 && st.wf == NONE32) {
+        const uint64_t wm = Wm & rest;
+        if (wm) st.wf = readlane(tidv, (uint32_t)__builtin_ctzll(wm));
+    }
+}
+
+DEV bool run_close(const RunState &st, uint32_t &ridx, uint32_t &ri1, uint32_t &ri2) {
+    if (st.t1 != NONE32 && (st.t0w || st.wf != NONE32)) {
+        ridx = st.idx;
+        ri1 = st.t0;
+        ri2 = st.t0w ? st.t1 : st.wf;
+        return true;
+    }
+    return false;
+}
+
+// First racy run (in sorted order) whose head lies in [a, b) of the sorted
+// array a_[0..cnt); runs starting before a belong to the previous wave and
+// the last run may extend past b.  Heads come from a ballot of key changes.
+DEV bool wave_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t a, uint32_t b, uint32_t &ridx,
+                         uint32_t &ri1, uint32_t &ri2) {
+    RunState st{false, 0, 0, NONE32, NONE32, false, false};
+    const uint32_t lane = lane_id();
+    for (uint32_t base = a; base < cnt; base += 64) {
+        if (!st.open && base >= b) break;
+        const uint32_t i = base + lane;
+        const bool valid = i < cnt;
+        const unsigned long long r = valid ? rec[i] : ~0ull;
+        const unsigned long long rp = (valid && i > 0) ? rec[i - 1] : ~0ull;
+        const uint32_t idx = rec_idx(r), tidv = rec_tid(r);
+        const bool head = valid && (i == 0 || rec_idx(rp) != idx);
+        const bool gch = valid && !head && rec_tid(rp) != tidv;
+        const uint64_t H = ballot(head), G = ballot(gch), Wm = ballot(valid && (r & 1ull));
+        const uint64_t V = ballot(valid);
+        const uint32_t nvalid = (uint32_t)__builtin_popcountll(V);   // valid lanes are a prefix
+        uint32_t pos = 0;
+        if (st.open) {
+            const uint64_t hn = H;
+            const uint32_t end = hn ? (uint32_t)__builtin_ctzll(hn) : nvalid;
+            run_segment(st, 0, end, G, Wm, tidv);
+            if (end < 64 && (end < nvalid || base + end >= cnt)) {
+                st.open = false;
+                if (run_close(st, ridx, ri1, ri2)) return true;
+            } else {
+                continue;   // run spans the whole chunk
+            }
+            pos = end;
+        }
+        const uint32_t lim = (b > base) ? (b - base < 64 ? b - base : 64) : 0;
+        uint64_t hs = H & bits_range(pos, lim);
+        while (hs) {
+            const uint32_t h = (uint32_t)__builtin_ctzll(hs);
+            const uint64_t nxt = H & bits_from(h + 1);
+            const uint32_t end = nxt ? (uint32_t)__builtin_ctzll(nxt) : nvalid;
+            hs &= bits_from(h + 1);
+            if (end == h + 1 && (end < nvalid || base + end >= cnt)) continue;   // single record: no race
+            st.open = true;
+            st.idx = readlane(idx, h);
+            st.t0 = readlane(tidv, h);
+            st.t1 = NONE32;
+            st.wf = NONE32;
+            st.in_t0 = true;
+            st.t0w = false;
+            run_segment(st, h, end, G, Wm, tidv);
+            if (end < nvalid || base + end >= cnt) {
+                st.open = false;
+                if (run_close(st, ridx, ri1, ri2)) return true;
+            } else {
+                break;   // continues in the next chunk
+            }
+        }
+    }
+    if (st.open && run_close(st, ridx, ri1, ri2)) return true;
+    return false;
+}
+
+// Workgroup-wide: first racy run of the sorted LDS array.  Returns found
+// (uniform across the block) and the run in *out (idx, i1, i2).
+DEV bool block_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t *lds_res /* 4 waves x 4 */,
+                          uint32_t &idx, uint32_t &i1, uint32_t &i2) {
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t per = (cnt + nw - 1) / nw;
+    const uint32_t a = wave * per, b = (a + per < cnt) ? a + per : cnt;
+    uint32_t ri = 0, r1 = 0, r2 = 0;
+    bool f = (a < cnt) ? wave_first_racy(rec, cnt, a, b, ri, r1, r2) : false;
+    if (lane_id() == 0) {
+        lds_res[wave * 4 + 0] = f ? 1u : 0u;
+        lds_res[wave * 4 + 1] = ri;
+        lds_res[wave * 4 + 2] = r1;
+        lds_res[wave * 4 + 3] = r2;
+    }
+    __syncthreads();
+    bool found = false;
+    for (uint32_t w = 0; w < nw; w++) {
+        if (lds_res[w * 4]) {
+            found = true;
+            idx = lds_res[w * 4 + 1];
+            i1 = lds_res[w * 4 + 2];
+            i2 = lds_res[w * 4 + 3];
+            break;
+        }
+    }
+    __syncthreads();
+    return found;
+}
+
+DEV void offer(Best *best, Cand *cand, uint32_t proto, uint32_t phase, uint32_t idx, uint32_t i1, uint32_t i2) {
+    const unsigned long long key = ((unsigned long long)phase << 32) | idx;
+    cand->key = key;
+    cand->pair = ((unsigned long long)i1 << 32) | i2;
+    cand->proto = proto;
+    atomicMin(&best[proto].key, key);
+}
+
+// =============================================================== fused path
+// One workgroup per unit: for every phase of the unit (small phases only),
+// evaluate all access events of the phase straight into LDS, sort them and
+// scan for the first racy group.  No record touches HBM.
+struct FusedSink {
+    unsigned long long *lds;
+    uint32_t *lds_n;
+    uint32_t tid;
+    DEV void acc(bool act, uint32_t idx, uint32_t mode) {
+        const uint64_t m = ballot(act);
+        if (m == 0) return;
+        uint32_t off = 0;
+        if (lane_id() == 0) off = atomicAdd(lds_n, (uint32_t)__builtin_popcountll(m));
+        off = __shfl(off, 0);
+        const uint32_t pos = off + mbcnt(m);
+        if (act && pos < (uint32_t)TILE)
+            lds[pos] = ((unsigned long long)idx << 32) | ((unsigned long long)tid << 1) | mode;
+    }
+};
+
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, const NestDesc *__restrict__ nests,
+                                               const ProtoDesc *__restrict__ protos,
+                                               const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
+                                               const unsigned long long *__restrict__ phase_counts,
+                                               Cand *__restrict__ cands, Best *__restrict__ best) {
+    __shared__ unsigned long long lds_rec[TILE];
+    __shared__ uint32_t lds_n;
+    __shared__ uint32_t lds_res[16];
+    const Unit u = units[blockIdx.x];
+    const ProtoDesc pd = protos[u.proto];
+    Cand *my = &cands[blockIdx.x];
+    if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = u.proto; }
+    bool have = false;
+    for (uint64_t k = u.k0; k < u.k1; k++) {
+        const unsigned long long cnt_k = phase_counts[k];
+        if (cnt_k == 0 || cnt_k > (unsigned long long)TILE) continue;   // empty or handled in HBM
+        if (threadIdx.x == 0) lds_n = 0;
+        __syncthreads();
+        for (uint32_t ni = 0; ni < pd.nnests; ni++) {
+            const NestDesc &nd = nests[pd.nest0 + ni];
+            if (k < nd.phase_base || k > nd.phase_last) continue;
+            const uint64_t fa = first_iter_at(nd, k);
+            if (fa >= nd.iters) continue;
+            T vars[MAXSLOTS];
+            for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+            load_fixed<T>(nd, fixed, vars);
+            Odo<T> odo;
+            odo.start(nd, fa, vars);
+            const uint32_t *leaf = code + nd.code_off;
+            for (uint64_t f = fa; f < nd.iters && odo.phase == k; f++) {
+                for (uint32_t t0 = 0; t0 < pd.n; t0 += WG) {
+                    const uint32_t tid = t0 + threadIdx.x;
+                    FusedSink sink{lds_rec, &lds_n, tid};
+                    T v2[MAXSLOTS];
+                    for (int s = 0; s < MAXSLOTS; s++) v2[s] = vars[s];
+                    bool ovf = false;
+                    run_leaf<T, WIDE>(leaf, v2, (T)tid, tid < pd.n, ovf, sink);
+                }
+                odo.next(nd, vars);
+            }
+        }
+        __syncthreads();
+        uint32_t cnt = lds_n;
+        if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: counted above
+        uint32_t npow = 1;
+        while (npow < cnt) npow <<= 1;
+        for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[i] = ~0ull;
+        __syncthreads();
+        lds_bitonic(lds_rec, npow);
+        uint32_t ridx, r1, r2;
+        const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
+        if (f && !have) {
+            have = true;
+            if (threadIdx.x == 0) offer(best, my, u.proto, (uint32_t)(k - pd.phase_off), ridx, r1, r2);
+        }
+        __syncthreads();
+    }
+}
+
+// =============================================================== partition
+__global__ __launch_bounds__(WG) void k_hist(const Seg *__restrict__ segs, const Chunk *__restrict__ chunks,
+                                              const unsigned long long *__restrict__ in,
+                                              unsigned long long *__restrict__ hist) {
+    __shared__ uint32_t h[RADIX];
+    const Chunk ch = chunks[blockIdx.x];
+    const Seg sg = segs[ch.seg];
+    for (uint32_t i = threadIdx.x; i < RADIX; i += WG) h[i] = 0;
+    __syncthreads();
+    const uint64_t b = sg.start + (uint64_t)ch.c * CHUNK;
+    const uint64_t e = (sg.start + sg.len < b + CHUNK) ? sg.start + sg.len : b + CHUNK;
+    const uint32_t mask = (1u << sg.dbits) - 1;
+    for (uint64_t i = b + threadIdx.x; i < e; i += WG) {
+        const uint32_t d = (rec_idx(in[i]) >> sg.shift) & mask;
+        atomicAdd(&h[d], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < (1u << sg.dbits); d += WG) hist[sg.hbase + (uint64_t)d * sg.nchunks + ch.c] = h[d];
+}
+
+__global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, const Chunk *__restrict__ chunks,
+                                                 const unsigned long long *__restrict__ in,
+                                                 const unsigned long long *__restrict__ offs,
+                                                 unsigned long long *__restrict__ out, unsigned long long cap) {
+    __shared__ uint32_t cur[RADIX];
+    __shared__ unsigned long long base[RADIX];
+    const Chunk ch = chunks[blockIdx.x];
+    const Seg sg = segs[ch.seg];
+    const uint32_t nd = 1u << sg.dbits;
+    for (uint32_t d = threadIdx.x; d < nd; d += WG) {
+        cur[d] = 0;
+        base[d] = offs[sg.hbase + (uint64_t)d * sg.nchunks + ch.c];
+    }
+    __syncthreads();
+    const uint64_t b = sg.start + (uint64_t)ch.c * CHUNK;
+    const uint64_t e = (sg.start + sg.len < b + CHUNK) ? sg.start + sg.len : b + CHUNK;
+    const uint32_t mask = nd - 1;
+    for (uint64_t i = b + threadIdx.x; i < e; i += WG) {
+        const unsigned long long r = in[i];
+        const uint32_t d = (rec_idx(r) >> sg.shift) & mask;
+        const uint32_t o = atomicAdd(&cur[d], 1u);
+        if (base[d] + o < cap) out[base[d] + o] = r;
+    }
+}
+
+// starts[s * 256 + d] = first output position of digit d of segment s
+// (the end of the last digit is the end of the segment's output).
+__global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const unsigned long long *__restrict__ offs,
+                         unsigned long long *__restrict__ starts) {
+    const uint32_t s = blockIdx.x;
+    if (s >= nsegs) return;
+    const Seg sg = segs[s];
+    const uint32_t nd = 1u << sg.dbits;
+    for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x)
+        starts[(uint64_t)s * RADIX + d] = offs[sg.hbase + (uint64_t)d * sg.nchunks];
+}
+
+// ================================================================== tiles
+__global__ __launch_bounds__(WG) void k_tile(const Tile *__restrict__ tiles, const unsigned long long *__restrict__ recs,
+                                              Cand *__restrict__ cands, Best *__restrict__ best) {
+    __shared__ unsigned long long lds_rec[TILE];
+    __shared__ uint32_t lds_res[16];
+    const Tile t = tiles[blockIdx.x];
+    Cand *my = &cands[blockIdx.x];
+    if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = t.proto; }
+    const uint32_t cnt = t.len;
+    uint32_t npow = 1;
+    while (npow < cnt) npow <<= 1;
+    for (uint32_t i = threadIdx.x; i < npow; i += WG) lds_rec[i] = i < cnt ? recs[t.start + i] : ~0ull;
+    __syncthreads();
+    lds_bitonic(lds_rec, npow);
+    uint32_t ridx, r1, r2;
+    const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
+    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, ridx, r1, r2);
+}
+
+// ============================================= single-index large groups
+// All records of a group share one index.  Pass 1: least tid, least writer,
+// largest tid.  Pass 2 (when the least tid writes): least tid != t0.
+DEV uint32_t wave_min(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w < v ? w : v; }
+    return v;
+}
+DEV uint32_t wave_max(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w > v ? w : v; }
+    return v;
+}
+
+__global__ __launch_bounds__(WG) void k_single1(const Group *__restrict__ groups, uint32_t ngroups,
+                                                 const unsigned long long *__restrict__ recs, SingleAcc *__restrict__ acc) {
+    const Group g = groups[blockIdx.y];
+    uint32_t t0 = NONE32, w0 = NONE32, tm = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < g.len; i += (uint64_t)gridDim.x * WG) {
+        const unsigned long long r = recs[g.start + i];
+        const uint32_t t = rec_tid(r);
+        t0 = t < t0 ? t : t0;
+        tm = t > tm ? t : tm;
+        if (r & 1ull) w0 = t < w0 ? t : w0;
+    }
+    t0 = wave_min(t0);
+    w0 = wave_min(w0);
+    tm = wave_max(tm);
+    if (lane_id() == 0) {
+        atomicMin(&acc[blockIdx.y].t0, t0);
+        atomicMin(&acc[blockIdx.y].w0, w0);
+        atomicMax(&acc[blockIdx.y].tmax, tm);
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_single2(const Group *__restrict__ groups, uint32_t ngroups,
+                                                 const unsigned long long *__restrict__ recs, SingleAcc *__restrict__ acc) {
+    const Group g = groups[blockIdx.y];
+    const uint32_t t0 = acc[blockIdx.y].t0;
+    uint32_t t1 = NONE32;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < g.len; i += (uint64_t)gridDim.x * WG) {
+        const uint32_t t = rec_tid(recs[g.start + i]);
+        if (t != t0 && t < t1) t1 = t;
+    }
+    t1 = wave_min(t1);
+    if (lane_id() == 0) atomicMin(&acc[blockIdx.y].t1, t1);
+}
+
+__global__ void k_single3(const Group *__restrict__ groups, uint32_t ngroups, const unsigned long long *__restrict__ recs,
+                          const SingleAcc *__restrict__ acc, Cand *__restrict__ cands, Best *__restrict__ best) {
+    const uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= ngroups) return;
+    const Group g = groups[gi];
+    const SingleAcc a = acc[gi];
+    Cand *my = &cands[gi];
+    my->key = ~0ull;
+    my->pair = 0;
+    my->proto = g.proto;
+    if (a.w0 != NONE32 && a.tmax != a.t0) {
+        const uint32_t idx = rec_idx(recs[g.start]);
+        offer(best, my, g.proto, g.phase, idx, a.t0, a.w0 == a.t0 ? a.t1 : a.w0);
+    }
+}
+
+// ==================================================== witness pair pick
+__global__ void k_pick(const Cand *__restrict__ cands, uint64_t n, Best *__restrict__ best) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Cand c = cands[i];
+    if (c.key != ~0ull && c.key == best[c.proto].key) best[c.proto].pair = c.pair;
+}
+
+// ================================================================ results
+__global__ void k_result(uint32_t count, const ResultIn *__restrict__ rin, const Best *__restrict__ best,
+                         drf_result_dev *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const ResultIn r = rin[i];
+    drf_result_dev o;
+    o.status = r.status;
+    o.racy = 0;
+    o.phase = o.index = o.tid_i = o.tid_j = NONE32;
+    o.num_records = 0;
+    o.num_phases = 0;
+    o.reserved = 0;
+    if (r.status == 0) {
+        const Best b = best[i];
+        o.num_records = r.num_records;
+        o.num_phases = r.num_phases;
+        if (b.key != ~0ull) {
+            o.racy = 1;
+            o.phase = (uint32_t)(b.key >> 32);
+            o.index = (uint32_t)b.key;
+            o.tid_i = (uint32_t)(b.pair >> 32);
+            o.tid_j = (uint32_t)b.pair;
+        }
+    }
+    out[i] = o;
+}
+
+// ================================================================== scan
+// Exclusive scan of u64 in place: block sums, recursive scan of the sums,
+// then add.  1024 elements per block (256 threads x 4).
+constexpr uint32_t SCAN_PER = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_block(unsigned long long *__restrict__ d, uint64_t n,
+                                                    unsigned long long *__restrict__ sums) {
+    __shared__ unsigned long long s[256];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_PER + threadIdx.x * 4;
+    unsigned long long v[4];
+    unsigned long long tot = 0;
+    for (int j = 0; j < 4; j++) { v[j] = (base + j < n) ? d[base + j] : 0; tot += v[j]; }
+    s[threadIdx.x] = tot;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        unsigned long long x = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += x;
+        __syncthreads();
+    }
+    unsigned long long run = s[threadIdx.x] - tot;   // exclusive prefix of this thread
+    for (int j = 0; j < 4; j++) {
+        if (base + j < n) d[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 255 && sums) sums[blockIdx.x] = s[255];
+}
+
+__global__ void k_scan_add(unsigned long long *__restrict__ d, uint64_t n, const unsigned long long *__restrict__ sums) {
+    const uint64_t i = (uint64_t)blockIdx.x * SCAN_PER + threadIdx.x;
+    const unsigned long long add = sums[blockIdx.x];
+    for (int j = 0; j < 4; j++) {
+        const uint64_t k = i + (uint64_t)j * 256;
+        if (k < n) d[k] += add;
+    }
+}
+
+// ============================================================== wrappers
+template <typename K, typename... A>
+static hipError_t launch(K kern, dim3 grid, dim3 block, hipStream_t s, A... args) {
+    if (grid.x == 0 || grid.y == 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, args...);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const Item *items, uint32_t nitems, bool wide, const NestDesc *nests,
+                        const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
+                        unsigned long long *phase_counts, uint32_t *item_cnt, uint32_t *proto_ovf,
+                        hipStream_t s) {
+    if (wide)
+        return launch(k_count<uint64_t, true>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                      phase_counts, item_cnt, proto_ovf);
+    return launch(k_count<uint32_t, false>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                  phase_counts, item_cnt, proto_ovf);
+}
+
+hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const NestDesc *nests,
+                       const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
+                       const uint32_t *item_cnt, const unsigned long long *big_base,
+                       unsigned long long *cursor, uint64_t win_lo, uint64_t win_n, unsigned long long *recs,
+                       unsigned long long cap, hipStream_t s) {
+    if (wide)
+        return launch(k_emit<uint64_t, true>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                      item_cnt, big_base, cursor, win_lo, win_n, recs, cap);
+    return launch(k_emit<uint32_t, false>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code, item_cnt,
+                  big_base, cursor, win_lo, win_n, recs, cap);
+}
+
+hipError_t launch_fused(const Unit *units, uint32_t nunits, bool wide, const NestDesc *nests,
+                        const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
+                        const unsigned long long *phase_counts, Cand *cands, Best *best, hipStream_t s) {
+    if (wide)
+        return launch(k_fused<uint64_t, true>, dim3(nunits), dim3(WG), s, units, nests, protos, fixed, code,
+                      phase_counts, cands, best);
+    return launch(k_fused<uint32_t, false>, dim3(nunits), dim3(WG), s, units, nests, protos, fixed, code,
+                  phase_counts, cands, best);
+}
+
+hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
+                       unsigned long long *hist, hipStream_t s) {
+    return launch(k_hist, dim3(nchunks), dim3(WG), s, segs, chunks, in, hist);
+}
+
+uint64_t scan_tmp_words(uint64_t n) {
+    uint64_t t = 0;
+    while (n > SCAN_PER) {
+        n = (n + SCAN_PER - 1) / SCAN_PER;
+        t += n;
+    }
+    return t + 1;
+}
+
+hipError_t launch_scan_u64(unsigned long long *data, uint64_t n, unsigned long long *tmp, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t nb = (n + SCAN_PER - 1) / SCAN_PER;
+    if (nb == 1) return launch(k_scan_block, dim3(1), dim3(256), s, data, n, (unsigned long long *)nullptr);
+    hipError_t e = launch(k_scan_block, dim3((uint32_t)nb), dim3(256), s, data, n, tmp);
+    if (e != hipSuccess) return e;
+    e = launch_scan_u64(tmp, nb, tmp + nb, s);
+    if (e != hipSuccess) return e;
+    return launch(k_scan_add, dim3((uint32_t)nb), dim3(256), s, data, n, (const unsigned long long *)tmp);
+}
+
+hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
+                          const unsigned long long *offs, unsigned long long *out, unsigned long long cap,
+                          hipStream_t s) {
+    return launch(k_scatter, dim3(nchunks), dim3(WG), s, segs, chunks, in, offs, out, cap);
+}
+
+hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs, unsigned long long *starts,
+                         hipStream_t s) {
+    return launch(k_starts, dim3(nsegs), dim3(256), s, segs, nsegs, offs, starts);
+}
+
+hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands, Best *best,
+                        hipStream_t s) {
+    return launch(k_tile, dim3(ntiles), dim3(WG), s, tiles, recs, cands, best);
+}
+
+hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned long long *recs, SingleAcc *acc,
+                         Cand *cands, Best *best, hipStream_t s) {
+    if (ngroups == 0) return hipSuccess;
+    hipError_t e = launch(k_single1, dim3(64, ngroups), dim3(WG), s, groups, ngroups, recs, acc);
+    if (e != hipSuccess) return e;
+    e = launch(k_single2, dim3(64, ngroups), dim3(WG), s, groups, ngroups, recs, acc);
+    if (e != hipSuccess) return e;
+    return launch(k_single3, dim3((ngroups + 255) / 256), dim3(256), s, groups, ngroups, recs,
+                  (const SingleAcc *)acc, cands, best);
+}
+
+hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, drf_result_dev *out, hipStream_t s) {
+    return launch(k_result, dim3((count + 255) / 256), dim3(256), s, count, rin, best, out);
+}
+
+hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s) {
+    return launch(k_pick, dim3((uint32_t)((ncands + 255) / 256)), dim3(256), s, cands, ncands, best);
+}
+
+}  // namespace drf

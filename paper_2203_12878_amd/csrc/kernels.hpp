@@ -1,0 +1,114 @@
+// Launch wrappers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "drf_layout.hpp"
+
+namespace drf {
+
+constexpr int WG = 256;            // lanes per workgroup of the evaluator kernels
+constexpr int MAXSPAN = 2048;      // phases one count / emit item may cover
+constexpr int TILE = 8192;         // access events one LDS tile holds (64 KiB)
+constexpr int CHUNK = 4096;        // records per partition chunk (one workgroup)
+constexpr int RADIX = 256;         // partition digit: 8 bits
+
+// Big-phase segment being partitioned by its next 8 (or fewer) index bits.
+struct Seg {
+    uint64_t start;       // first record in the input buffer
+    uint64_t len;
+    uint64_t hbase;       // histogram base: digit-major, chunk-minor
+    uint32_t nchunks;
+    uint32_t proto;
+    uint32_t phase;       // local phase
+    uint32_t shift;       // digit = (index >> shift) & (2^dbits - 1)
+    uint32_t dbits;
+    uint32_t pad;
+};
+
+struct Chunk {
+    uint32_t seg;
+    uint32_t c;           // chunk number within the segment
+};
+
+// Records of one phase (or a sub-bucket of it) that fit one LDS tile, or
+// a group of one index value that does not.
+struct Tile {
+    uint64_t start;
+    uint32_t len;
+    uint32_t proto;
+    uint32_t phase;       // local phase
+    uint32_t pad;
+};
+
+struct Group {
+    uint64_t start;
+    uint64_t len;
+    uint32_t proto;
+    uint32_t phase;
+};
+
+struct Best {             // per protocol
+    unsigned long long key;   // local phase << 32 | index, ~0 when none
+    unsigned long long pair;  // tid_i << 32 | tid_j
+};
+
+struct SingleAcc {        // per single-index group
+    uint32_t t0, w0, tmax, t1;
+};
+
+hipError_t launch_count(const Item *items, uint32_t nitems, bool wide, const NestDesc *nests,
+                        const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
+                        unsigned long long *phase_counts, uint32_t *item_cnt, uint32_t *proto_ovf,
+                        hipStream_t s);
+
+hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const NestDesc *nests,
+                       const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
+                       const uint32_t *item_cnt, const unsigned long long *big_base,
+                       unsigned long long *cursor, uint64_t win_lo, uint64_t win_n, unsigned long long *recs,
+                       unsigned long long cap, hipStream_t s);
+
+hipError_t launch_fused(const Unit *units, uint32_t nunits, bool wide, const NestDesc *nests,
+                        const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
+                        const unsigned long long *phase_counts, Cand *cands, Best *best, hipStream_t s);
+
+hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
+                       unsigned long long *hist, hipStream_t s);
+
+hipError_t launch_scan_u64(unsigned long long *data, uint64_t n, unsigned long long *tmp, hipStream_t s);
+uint64_t scan_tmp_words(uint64_t n);
+
+hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
+                          const unsigned long long *offs, unsigned long long *out, unsigned long long cap,
+                          hipStream_t s);
+
+hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs,
+                         unsigned long long *starts, hipStream_t s);
+
+hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands,
+                        Best *best, hipStream_t s);
+
+hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned long long *recs,
+                         SingleAcc *acc, Cand *cands, Best *best, hipStream_t s);
+
+hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s);
+
+// Final per-protocol result (same layout as drf_result of the C ABI).
+struct drf_result_dev {
+    int32_t status;
+    uint32_t racy;
+    uint32_t phase, index, tid_i, tid_j;
+    uint64_t num_records;
+    uint32_t num_phases;
+    uint32_t reserved;
+};
+
+struct ResultIn {
+    int32_t status;
+    uint32_t num_phases;
+    uint64_t num_records;
+};
+
+hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, drf_result_dev *out, hipStream_t s);
+
+}  // namespace drf

@@ -1,0 +1,232 @@
+"""Python binding of libdrf (ctypes).  Argument marshalling only: every step
+of the check runs in the library's host code and gfx950 kernels.  PyTorch
+provides device memory and streams.
+
+    chk = Checker(device=0)
+    r = chk.check("(seq (wr tid) (sync) (rd (mod (+ tid 1) 8)))", 8)
+    r.racy, r.witness, r.phase_counts, r.num_records
+
+There is no CPU fallback: without libdrf.so or a GPU this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple, Union
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdrf.so")
+
+OK = 0
+E_ARG, E_BYTECODE, E_UNBOUND, E_SHADOW, E_SYNC_IN_U = -1, -2, -3, -4, -5
+E_DIVERGENT, E_RANGE, E_NOMEM, E_HIP, E_LIMIT = -6, -7, -8, -9, -10
+NONE = 0xFFFFFFFF
+
+
+class DrfError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s failed with code %d" % (what, code))
+        self.code = code
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("num_phases", ctypes.c_uint32), ("index_bits", ctypes.c_uint32),
+                ("wide", ctypes.c_uint32), ("max_records", ctypes.c_uint64), ("nests", ctypes.c_uint64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("racy", ctypes.c_uint32), ("phase", ctypes.c_uint32),
+                ("index", ctypes.c_uint32), ("tid_i", ctypes.c_uint32), ("tid_j", ctypes.c_uint32),
+                ("num_records", ctypes.c_uint64), ("num_phases", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+RESULT_DTYPE = np.dtype([("status", "<i4"), ("racy", "<u4"), ("phase", "<u4"), ("index", "<u4"),
+                         ("tid_i", "<u4"), ("tid_j", "<u4"), ("num_records", "<u8"), ("num_phases", "<u4"),
+                         ("reserved", "<u4")])
+assert RESULT_DTYPE.itemsize == ctypes.sizeof(_Result) == 40
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdrf.so (built in-tree by paper_2203_12878_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdrf.so is not built (run paper_2203_12878_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.drf_version.restype = ctypes.c_char_p
+        L.drf_compile_text.argtypes = [ctypes.c_char_p, ctypes.c_size_t, u32p, ctypes.c_uint32, u32p]
+        L.drf_plan_protocol.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Plan)]
+        L.drf_ctx_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]
+        L.drf_ctx_destroy.argtypes = [ctypes.c_void_p]
+        L.drf_check_protocol.argtypes = [ctypes.c_void_p, u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.drf_check_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        for f in ("drf_compile_text", "drf_plan_protocol", "drf_ctx_create", "drf_ctx_destroy",
+                  "drf_check_protocol", "drf_check_batch"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _u32p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _u64p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def compile_text(text: str) -> np.ndarray:
+    """Text form -> bytecode (uint32 array)."""
+    L = lib()
+    b = text.encode()
+    n = ctypes.c_uint32(0)
+    cap = max(64, 4 * len(b) + 16)
+    out = np.zeros(cap, dtype=np.uint32)
+    rc = L.drf_compile_text(b, len(b), _u32p(out), cap, ctypes.byref(n))
+    if rc == E_NOMEM:
+        out = np.zeros(n.value, dtype=np.uint32)
+        rc = L.drf_compile_text(b, len(b), _u32p(out), n.value, ctypes.byref(n))
+    if rc != OK:
+        raise DrfError(rc, "drf_compile_text")
+    return out[:n.value].copy()
+
+
+def plan(code: Union[str, np.ndarray], n: int) -> Plan:
+    code = compile_text(code) if isinstance(code, str) else np.ascontiguousarray(code, dtype=np.uint32)
+    p = Plan()
+    rc = lib().drf_plan_protocol(_u32p(code), len(code), n, ctypes.byref(p))
+    if rc != OK:
+        raise DrfError(rc, "drf_plan_protocol")
+    return p
+
+
+@dataclass
+class CheckResult:
+    status: int
+    racy: int = 0
+    witness: Optional[Tuple[int, int, int, int]] = None
+    phase_counts: List[int] = field(default_factory=list)
+    num_records: int = 0
+
+    def key(self):
+        return (self.status, self.racy, self.witness, tuple(self.phase_counts), self.num_records)
+
+
+class Batch:
+    """Bytecode of several protocols packed for drf_check_batch, with the
+    device result and phase-count buffers it needs."""
+
+    def __init__(self, items: Sequence[Tuple[Union[str, np.ndarray], int]], device: int = 0):
+        import torch
+        codes = [compile_text(c) if isinstance(c, str) else np.ascontiguousarray(c, dtype=np.uint32)
+                 for c, _ in items]
+        self.count = len(items)
+        self.nthreads = np.array([int(n) for _, n in items], dtype=np.uint32)
+        self.code_off = np.zeros(self.count + 1, dtype=np.uint64)
+        if codes:
+            self.code_off[1:] = np.cumsum([len(c) for c in codes])
+        self.code = np.concatenate(codes).astype(np.uint32) if codes else np.zeros(1, np.uint32)
+        self.plans = [plan(c, int(n)) for c, n in zip(codes, self.nthreads)]
+        self.phase_off = np.zeros(self.count + 1, dtype=np.uint64)
+        nph = [p.num_phases if p.status == 0 else 0 for p in self.plans]
+        if nph:
+            self.phase_off[1:] = np.cumsum(nph)
+        self.total_phases = int(self.phase_off[-1])
+        dev = torch.device("cuda", device)
+        self.results = torch.zeros(max(1, self.count) * 40, dtype=torch.uint8, device=dev)
+        self.counts = torch.zeros(max(1, self.total_phases), dtype=torch.int64, device=dev)
+
+    def collect(self) -> List[CheckResult]:
+        """Copy results back (after the stream work has finished)."""
+        res = np.frombuffer(self.results.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[:self.count]
+        counts = self.counts.cpu().numpy().view(np.uint64)
+        out = []
+        for i in range(self.count):
+            r = res[i]
+            st = int(r["status"])
+            if st != 0:
+                out.append(CheckResult(st))
+                continue
+            wit = (int(r["phase"]), int(r["index"]), int(r["tid_i"]), int(r["tid_j"])) if r["racy"] else None
+            a = int(self.phase_off[i])
+            pc = [int(x) for x in counts[a:a + int(r["num_phases"])]]
+            out.append(CheckResult(0, int(r["racy"]), wit, pc, int(r["num_records"])))
+        return out
+
+
+class Checker:
+    """Owns a libdrf context on one HIP device (one per host thread)."""
+
+    def __init__(self, device: int = 0, scratch_limit: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libdrf needs an MI355X")
+        self.device = device
+        self._ctx = ctypes.c_void_p()
+        rc = lib().drf_ctx_create(device, int(scratch_limit), ctypes.byref(self._ctx))
+        if rc != OK:
+            raise DrfError(rc, "drf_ctx_create")
+
+    def close(self):
+        if self._ctx:
+            lib().drf_ctx_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def run_batch(self, b: Batch, stream=None) -> None:
+        """Enqueue drf_check_batch for a prepared batch (results valid after
+        the stream is synchronized)."""
+        rc = lib().drf_check_batch(self._ctx, _u32p(b.code), _u64p(b.code_off), _u32p(b.nthreads), b.count,
+                                   ctypes.c_void_p(b.results.data_ptr()), ctypes.c_void_p(b.counts.data_ptr()),
+                                   b.total_phases, self._stream(stream))
+        if rc != OK:
+            raise DrfError(rc, "drf_check_batch")
+
+    def run_plain(self, b: Batch, stream=None) -> None:
+        """The plain path: drf_check_protocol once per protocol of the batch."""
+        L = lib()
+        s = self._stream(stream)
+        base_r = b.results.data_ptr()
+        base_c = b.counts.data_ptr()
+        for i in range(b.count):
+            a, e = int(b.code_off[i]), int(b.code_off[i + 1])
+            code = b.code[a:e]
+            rc = L.drf_check_protocol(self._ctx, _u32p(code), e - a, int(b.nthreads[i]),
+                                      ctypes.c_void_p(base_r + 40 * i),
+                                      ctypes.c_void_p(base_c + 8 * int(b.phase_off[i])),
+                                      int(b.phase_off[i + 1] - b.phase_off[i]), s)
+            if rc != OK:
+                raise DrfError(rc, "drf_check_protocol")
+
+    def check_batch(self, items: Sequence[Tuple[Union[str, np.ndarray], int]], stream=None) -> List[CheckResult]:
+        import torch
+        b = Batch(items, self.device)
+        self.run_batch(b, stream)
+        (stream or torch.cuda.current_stream(self.device)).synchronize()
+        return b.collect()
+
+    def check(self, proto: Union[str, np.ndarray], n: int, stream=None) -> CheckResult:
+        import torch
+        b = Batch([(proto, n)], self.device)
+        self.run_plain(b, stream)
+        (stream or torch.cuda.current_stream(self.device)).synchronize()
+        return b.collect()[0]

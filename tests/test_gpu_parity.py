@@ -1,0 +1,112 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit-exact on every output (status, race flag, witness, per-phase counts,
+record count)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import o2, ref
+from paper_2203_12878_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def chk():
+    from paper_2203_12878_amd import drf
+    c = drf.Checker(0)
+    yield c
+    c.close()
+
+
+def _same(got, want, items):
+    bad = [(t[:120], n, g, e) for (t, n), g, e in zip(items, got, want) if g.key() != e.key()]
+    assert not bad, "%d mismatches, first: %r" % (len(bad), bad[:3])
+
+
+def test_paper_examples(chk):
+    import test_oracle as T
+    golden = T.load_golden()
+    items = [(c["text"], c["n"]) for c in golden]
+    got = chk.check_batch(items)
+    for c, g in zip(golden, got):
+        e = c["expect"]
+        assert g.status == e["status"], c["name"]
+        if e["status"] == 0:
+            assert g.racy == e["racy"] and list(g.phase_counts) == e["phase_counts"], c["name"]
+            assert g.witness == (tuple(e["witness"]) if e["witness"] else None), c["name"]
+
+
+def test_closed_forms(chk):
+    import test_oracle as T
+    cases = T.closed_form_cases()
+    got = chk.check_batch([(t, n) for _, t, n, *_ in cases])
+    for (name, t, n, racy, wit, counts), g in zip(cases, got):
+        assert (g.status, g.racy, g.witness, list(g.phase_counts)) == (0, racy, wit, counts), name
+    errs = chk.check_batch([(t, n) for t, n, _ in T.ERROR_CASES])
+    for (t, n, st), g in zip(T.ERROR_CASES, errs):
+        assert g.status == st, t
+
+
+def test_tiny_enumeration(chk):
+    items = list(w.enumerate_tiny())
+    want = o2.check_many(items, jobs=16)
+    got = chk.check_batch(items)
+    _same(got, want, items)
+
+
+def test_plain_path_equals_batch(chk):
+    items = list(w.enumerate_tiny(limit_random=400, seed=3))[-400:]
+    items += [w.gen_small(1), w.tree_protocol(9, 2)]
+    batch = chk.check_batch(items)
+    for (t, n), b in zip(items, batch):
+        assert chk.check(t, n).key() == b.key(), t
+
+
+def test_small_config_seeds(chk):
+    items = [w.gen_small(s) for s in range(10)]
+    _same(chk.check_batch(items), o2.check_many(items, jobs=10), items)
+
+
+def test_big_phase_path(chk):
+    # phases with more events than one LDS tile: emitted to HBM and
+    # partitioned by index bits; a hot cell makes a single-index group
+    items = []
+    for s in range(3):
+        t, _ = w.gen_large(s, n=4096, lo_prod=2, hi_prod=6)
+        items.append((t, 4096))
+    items += [("(foru x 0 3 (seq (wr 5) (rd (+ tid x))))", 9000),           # 27000 events on cell 5
+              ("(seq (rd 77) (if (= tid 8191) (wr 77) (skip)))", 20000),    # last reader writes
+              ("(seq (wr tid) (rd (mod (* tid 7) 20011)))", 20011),
+              ("(rd 0)", 30000),                                           # index_bits 0, read only
+              ("(seq (rd 0) (if (= tid 29999) (wr 0) (skip)))", 30000),
+              ("(fors x 0 3 (seq (wr (+ (* tid 3) x)) (sync) (rd (+ (* tid 3) x))))", 12000)]
+    items += [w.tree_protocol(16, r) for r in (None, 0, 3, 14, 15)]
+    _same(chk.check_batch(items), o2.check_many(items, jobs=8), items)
+
+
+def test_tree_batch_closed_form(chk):
+    import test_oracle as T
+    batch = w.gen_tree_batch(0, count=64, kmax=16)
+    got = chk.check_batch([(t, n) for t, n, _ in batch])
+    for (t, n, lab), g in zip(batch, got):
+        k = n.bit_length() - 1
+        removed = None if lab == "drf" else int(lab.split("@")[1])
+        racy, wit, counts = T.tree_expect(k, removed)
+        assert (g.status, g.racy, g.witness, list(g.phase_counts)) == (0, racy, wit, counts), lab
+
+
+def test_mixed_batch_subset(chk):
+    batch = w.gen_mixed_batch(0, count=256)
+    items = [(t, n) for t, n, _ in batch]
+    got = chk.check_batch(items)
+    # oracle on the ones it finishes quickly
+    small = [i for i, (t, n) in enumerate(items) if got[i].num_records < 3_000_000]
+    want = o2.check_many([items[i] for i in small], jobs=16)
+    _same([got[i] for i in small], want, [items[i] for i in small])
+    for (t, n, lab), g in zip(batch, got):
+        assert g.status == 0 and g.racy == (lab != "drf"), lab
