@@ -50,7 +50,7 @@ struct drf_ctx {
 namespace {
 
 constexpr uint64_t ITEM_EVENTS = 1ull << 16;   // target access events per count/emit item
-constexpr uint64_t UNIT_EVENTS = 1ull << 16;   // target access events per fused unit
+constexpr uint64_t UNIT_EVENTS = 1ull << 12;   // target access events per fused unit
 constexpr uint64_t CAND_CAP = 1ull << 20;      // candidates per launch
 constexpr uint64_t ALIGN = 256;
 
@@ -474,14 +474,26 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
         for (size_t s2 = 0; s2 < segs.size(); s2++) {
             const Seg &sg = segs[s2];
             const uint32_t nd = 1u << sg.dbits;
+            // consecutive small buckets of one segment are contiguous and
+            // hold disjoint index values: one tile takes several of them
+            Tile cur{0, 0, sg.proto, sg.phase, 0};
             for (uint32_t d = 0; d < nd; d++) {
                 const uint64_t a = starts[s2 * RADIX + d];
                 const uint64_t e = (d + 1 < nd) ? starts[s2 * RADIX + d + 1] : out_start[s2] + sg.len;
                 const uint64_t len = e - a;
                 if (len == 0) continue;
                 if (len <= (uint64_t)TILE) {
-                    tiles.push_back(Tile{a, (uint32_t)len, sg.proto, sg.phase, 0});
-                } else if (sg.shift == 0) {
+                    if (cur.len && cur.start + cur.len == a && cur.len + len <= (uint64_t)TILE) {
+                        cur.len += (uint32_t)len;
+                    } else {
+                        if (cur.len) tiles.push_back(cur);
+                        cur.start = a;
+                        cur.len = (uint32_t)len;
+                    }
+                    continue;
+                }
+                if (cur.len) { tiles.push_back(cur); cur.len = 0; }
+                if (sg.shift == 0) {
                     g2.push_back(Group{a, len, sg.proto, sg.phase});
                 } else {
                     Seg ns{};
@@ -494,6 +506,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
                     next.push_back(ns);
                 }
             }
+            if (cur.len) tiles.push_back(cur);
         }
         run_tiles(tiles, out);
         if (!g2.empty()) run_groups(g2, out);

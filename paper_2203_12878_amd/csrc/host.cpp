@@ -655,9 +655,65 @@ struct Planner {
 
     static bool is_const(const XNode &x) { return x.op == B_CONST32 || x.op == B_CONST64; }
 
+    // Affine flattening: e = c0 + sum coef * leaf over tid and loop
+    // variables, through + and multiplication by constants.  With 64-bit
+    // overflow checks every multiplier must be >= 1, so that every
+    // intermediate value of the original tree is at most the final sum and
+    // checking the sum alone is exact.
+    bool affine(int e, u128 mult, std::vector<std::pair<uint32_t, u128>> &terms, u128 &c0, bool wide) {
+        const XNode &x = ir.x[e];
+        switch (x.op) {
+        case B_CONST32: case B_CONST64:
+            if (x.val >= VALUE_LIMIT) return false;
+            c0 = sat(c0 + smul(mult, x.val));
+            return true;
+        case B_TID: case B_VAR: {
+            const uint32_t v = x.op == B_TID ? NONE32 : x.slot;
+            for (auto &t : terms) if (t.first == v) { t.second = sat(t.second + mult); return true; }
+            terms.push_back({v, mult});
+            return true;
+        }
+        case B_ADD: return affine(x.a, mult, terms, c0, wide) && affine(x.b, mult, terms, c0, wide);
+        case B_MUL: {
+            const XNode &A = ir.x[x.a], &B = ir.x[x.b];
+            if (is_const(B) && B.val < VALUE_LIMIT && (!wide || B.val >= 1))
+                return affine(x.a, smul(mult, B.val), terms, c0, wide);
+            if (is_const(A) && A.val < VALUE_LIMIT && (!wide || A.val >= 1))
+                return affine(x.b, smul(mult, A.val), terms, c0, wide);
+            return false;
+        }
+        }
+        return false;
+    }
+
+    bool gen_affine(int e) {
+        const XNode &x = ir.x[e];
+        if (x.op != B_ADD && x.op != B_MUL) return false;
+        std::vector<std::pair<uint32_t, u128>> terms;
+        u128 c0 = 0;
+        if (!affine(e, 1, terms, c0, plan.wide)) return false;
+        if (!plan.wide) {
+            std::vector<std::pair<uint32_t, u128>> nz;
+            for (auto &t : terms) if (t.second) nz.push_back(t);
+            terms.swap(nz);
+        }
+        const u128 climit = plan.wide ? (u128)VALUE_LIMIT : (u128)1 << 32;
+        if (c0 >= climit || terms.size() > 8) return false;
+        for (auto &t : terms) if (t.second >= ((u128)1 << 32)) return false;
+        auto &c = *code;
+        c.push_back(X_AFF);
+        c.push_back((uint32_t)terms.size());
+        c.push_back((uint32_t)(uint64_t)c0);
+        c.push_back((uint32_t)((uint64_t)c0 >> 32));
+        for (auto &t : terms) { c.push_back(t.first); c.push_back((uint32_t)t.second); }
+        push_depth(1);
+        return true;
+    }
+
     void gen_x(int e) {
         const XNode &x = ir.x[e];
         auto &c = *code;
+        if (gen_affine(e)) return;
         switch (x.op) {
         case B_CONST32: case B_CONST64:
             c.push_back(X_CONST); c.push_back((uint32_t)x.val); c.push_back((uint32_t)(x.val >> 32));
@@ -767,7 +823,7 @@ struct Planner {
         walk(ir.root, cursor);
         if (status) return;
         plan.num_phases = cursor + 1;
-        // per nest: iterations, last phase, intervals, event bound, leaf code
+        // per nest: iterations, last phase, intervals, event bound
         for (Nest &ne : plan.nests) {
             u128 it = 1;
             u128 last = ne.phase_base;
@@ -783,6 +839,12 @@ struct Planner {
             ne.rec_bound = (uint32_t)std::min<u128>(per, 0xFFFFFFFFu);
             events = sat(events + smul(smul(per, n), it));
             total_work = sat(total_work + smul(smul(sat(work + per + 1), n), it));
+        }
+        if (events >= MAX_EVENTS || total_work >= MAX_EVENTS * 4) { fail(DRF_E_LIMIT); return; }
+        plan.max_records = (uint64_t)events;
+        plan.wide = iv_max >= (u128)(1ull << 32);
+        // leaf code (the 32- or 64-bit evaluator decides what may be folded)
+        for (Nest &ne : plan.nests) {
             auto f = code_of_leaf.find(ne.leaf);
             if (f == code_of_leaf.end()) {
                 plan.leaf_code.emplace_back();
@@ -799,9 +861,6 @@ struct Planner {
             }
             if (status) return;
         }
-        if (events >= MAX_EVENTS || total_work >= MAX_EVENTS * 4) { fail(DRF_E_LIMIT); return; }
-        plan.max_records = (uint64_t)events;
-        plan.wide = iv_max >= (u128)(1ull << 32);
         uint32_t bits = 0;
         while (bits < 32 && (max_index >> bits) != 0) bits++;
         plan.index_bits = bits;

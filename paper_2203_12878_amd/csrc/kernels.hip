@@ -86,6 +86,31 @@ DEV T eval_expr(const uint32_t *__restrict__ c, uint32_t len, const T *vars, T t
             }
             st[sp - 1] = r;
             i += 2;
+        } else if (op == X_AFF) {
+            // c0 + sum coef * var (var NONE32 = tid); multipliers below 2^32
+            const uint32_t nt = rfl(c[i + 1]);
+            T acc;
+            if constexpr (WIDE) {
+                acc = ((uint64_t)rfl(c[i + 3]) << 32) | (uint64_t)rfl(c[i + 2]);
+            } else {
+                acc = rfl(c[i + 2]);
+            }
+            for (uint32_t t = 0; t < nt; t++) {
+                const uint32_t v = rfl(c[i + 4 + 2 * t]);
+                const T k = (T)rfl(c[i + 5 + 2 * t]);
+                const uint32_t vi = (v == NONE32) ? 0u : v;
+                const T x = (v == NONE32) ? tid : vars[vi];
+                if constexpr (WIDE) {
+                    const T p = x * k;
+                    o |= (__umul64hi(x, k) != 0) || ((p >> 63) != 0);
+                    acc += p;
+                    o |= (acc >> 63) != 0;
+                } else {
+                    acc += x * k;
+                }
+            }
+            st[sp++] = acc;
+            i += 4 + 2 * nt;
         } else if (op == X_TRUE || op == X_FALSE) {
             st[sp++] = (op == X_TRUE) ? 1 : 0;
             i += 1;
@@ -320,9 +345,8 @@ __global__ __launch_bounds__(WG) void k_count(const Item *__restrict__ items, co
             sink.n = 0;
             cur = odo.phase;
         }
-        T v2[MAXSLOTS];
-        for (int s = 0; s < MAXSLOTS; s++) v2[s] = vars[s];
-        run_leaf<T, WIDE>(leaf, v2, (T)tid, act0, ovf, sink);
+        // leaf loops never write for^S slots (binders are distinct)
+        run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
         odo.next(nd, vars);
     }
     if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
@@ -397,28 +421,90 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
         if (b != ~0ull) {
             sink.cur = &lds_cur[i];
             sink.base = b;
-            T v2[MAXSLOTS];
-            for (int s = 0; s < MAXSLOTS; s++) v2[s] = vars[s];
-            run_leaf<T, WIDE>(leaf, v2, (T)tid, act0, ovf, sink);
+            run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
         }
         odo.next(nd, vars);
     }
 }
 
 // ======================================================= LDS sort + scan
-// Bitonic sort of n (power of two) u64 keys in LDS by the whole workgroup.
-DEV void lds_bitonic(unsigned long long *a, uint32_t n) {
+// Bitonic sort of n = 256 * E u64 keys in LDS by a 256-thread workgroup.
+// Thread t keeps a[E*t .. E*t+E) in registers for every stride below E;
+// larger strides exchange through LDS, with all loads of a stage issued
+// before any store (pairs of one stage are disjoint).
+template <int E>
+DEV void block_sort_e(unsigned long long *a, uint32_t n) {
+    constexpr int PAIRS = (E / 2 > 0) ? E / 2 : 1;
+    const uint32_t t = threadIdx.x;
+    const uint32_t g0 = t * E;
+    const uint32_t half = n >> 1;
+    unsigned long long v[E];
+#pragma unroll
+    for (int j = 0; j < E; j++) v[j] = a[g0 + j];
     for (uint32_t size = 2; size <= n; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
-                const uint32_t lo = 2 * i - (i & (stride - 1));
-                const uint32_t hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const unsigned long long x = a[lo], y = a[hi];
-                if ((x > y) == asc) { a[lo] = y; a[hi] = x; }
-            }
+        if ((size >> 1) >= (uint32_t)E) {
             __syncthreads();
+#pragma unroll
+            for (int j = 0; j < E; j++) a[g0 + j] = v[j];
+            __syncthreads();
+            for (uint32_t stride = size >> 1; stride >= (uint32_t)E; stride >>= 1) {
+                unsigned long long x[PAIRS], y[PAIRS];
+                uint32_t lo[PAIRS];
+#pragma unroll
+                for (int j = 0; j < PAIRS; j++) {
+                    const uint32_t i = t + (uint32_t)j * 256u;
+                    lo[j] = 2 * i - (i & (stride - 1));
+                    if (i < half) {
+                        x[j] = a[lo[j]];
+                        y[j] = a[lo[j] + stride];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PAIRS; j++) {
+                    const uint32_t i = t + (uint32_t)j * 256u;
+                    if (i < half) {
+                        const bool asc = (lo[j] & size) == 0;
+                        const bool sw = (x[j] > y[j]) == asc;
+                        a[lo[j]] = sw ? y[j] : x[j];
+                        a[lo[j] + stride] = sw ? x[j] : y[j];
+                    }
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int j = 0; j < E; j++) v[j] = a[g0 + j];
         }
+#pragma unroll
+        for (int st = E / 2; st >= 1; st >>= 1) {
+            if ((uint32_t)st <= (size >> 1)) {
+#pragma unroll
+                for (int j = 0; j < E; j++) {
+                    if ((j & st) == 0) {
+                        const bool asc = ((g0 + (uint32_t)j) & size) == 0;
+                        const unsigned long long x = v[j], y = v[j + st];
+                        const bool sw = (x > y) == asc;
+                        v[j] = sw ? y : x;
+                        v[j + st] = sw ? x : y;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; j++) a[g0 + j] = v[j];
+    __syncthreads();
+}
+
+// Sorts a[0..npow) (npow a power of two, 256 <= npow <= TILE).
+DEV void block_sort(unsigned long long *a, uint32_t npow) {
+    switch (npow >> 8) {
+    case 1: block_sort_e<1>(a, npow); break;
+    case 2: block_sort_e<2>(a, npow); break;
+    case 4: block_sort_e<4>(a, npow); break;
+    case 8: block_sort_e<8>(a, npow); break;
+    case 16: block_sort_e<16>(a, npow); break;
+    default: block_sort_e<32>(a, npow); break;
     }
 }
 
@@ -621,10 +707,8 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, co
                 for (uint32_t t0 = 0; t0 < pd.n; t0 += WG) {
                     const uint32_t tid = t0 + threadIdx.x;
                     FusedSink sink{lds_rec, &lds_n, tid};
-                    T v2[MAXSLOTS];
-                    for (int s = 0; s < MAXSLOTS; s++) v2[s] = vars[s];
                     bool ovf = false;
-                    run_leaf<T, WIDE>(leaf, v2, (T)tid, tid < pd.n, ovf, sink);
+                    run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
                 }
                 odo.next(nd, vars);
             }
@@ -632,11 +716,11 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, co
         __syncthreads();
         uint32_t cnt = lds_n;
         if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: counted above
-        uint32_t npow = 1;
+        uint32_t npow = 256;
         while (npow < cnt) npow <<= 1;
         for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[i] = ~0ull;
         __syncthreads();
-        lds_bitonic(lds_rec, npow);
+        block_sort(lds_rec, npow);
         uint32_t ridx, r1, r2;
         const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
         if (f && !have) {
@@ -713,11 +797,11 @@ __global__ __launch_bounds__(WG) void k_tile(const Tile *__restrict__ tiles, con
     Cand *my = &cands[blockIdx.x];
     if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = t.proto; }
     const uint32_t cnt = t.len;
-    uint32_t npow = 1;
+    uint32_t npow = 256;
     while (npow < cnt) npow <<= 1;
     for (uint32_t i = threadIdx.x; i < npow; i += WG) lds_rec[i] = i < cnt ? recs[t.start + i] : ~0ull;
     __syncthreads();
-    lds_bitonic(lds_rec, npow);
+    block_sort(lds_rec, npow);
     uint32_t ridx, r1, r2;
     const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
     if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, ridx, r1, r2);
