@@ -116,7 +116,8 @@ typedef struct {
     uint32_t wide;         /* 1 when values may reach 2^32 (64-bit evaluator) */
     uint64_t max_records;  /* upper bound on executed access events */
     uint64_t nests;        /* unsynchronized leaves times host-unrolled iterations */
-} drf_plan;                /* 32 bytes */
+    uint64_t max_phase_records;  /* upper bound on the events of any one phase */
+} drf_plan;                /* 40 bytes */
 
 /* Result of one protocol. */
 typedef struct {
@@ -183,6 +184,42 @@ int drf_ctx_set_profiling(drf_ctx *ctx, int on);
 /* Copies up to cap entries into out, sets *n to the number of classes and
  * resets the totals when reset != 0. */
 int drf_ctx_kernel_stats(drf_ctx *ctx, drf_kernel_stat *out, uint32_t cap, uint32_t *n, int reset);
+
+/* Prepared batch: checks the batch once (like drf_check_batch, with the
+ * same outputs in the same caller buffers) while recording every device
+ * operation, then captures that sequence into one hipGraph.  Each
+ * drf_run_prepared replays the whole device work of the check (count,
+ * fused, emit, partition, tiles, witness, results) as one graph launch on
+ * `stream` and rewrites the same outputs; the host plan and partition lists
+ * of the first run are reused.  The prepared batch owns its scratch memory
+ * (not the context's pools) and keeps d_results / d_phase_counts pointers:
+ * they must stay valid until drf_prepared_destroy.  Replays of one prepared
+ * batch must not overlap (run them on one stream). */
+typedef struct drf_prepared drf_prepared;
+
+int drf_prepare_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                      uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
+                      void *stream, drf_prepared **out);
+int drf_run_prepared(drf_prepared *p, void *stream);
+int drf_prepared_destroy(drf_prepared *p);
+/* Number of device operations in the prepared graph. */
+uint64_t drf_prepared_launches(const drf_prepared *p);
+
+/* Tuning of a context (what the autotuner sets).  tile_events: most access
+ * events of one phase (or bucket) sorted in one LDS tile, a power of two in
+ * [256, 8192]; digit_bits: index bits per MSD partition level, 4..10;
+ * unit_events / item_events: target events per fused unit / per count and
+ * emit work item.  Zero fields keep their value; DRF_E_ARG when out of
+ * range (nothing changes then). */
+typedef struct {
+    uint32_t tile_events;
+    uint32_t digit_bits;
+    uint32_t unit_events;
+    uint32_t item_events;
+} drf_tuning;
+
+int drf_ctx_set_tuning(drf_ctx *ctx, const drf_tuning *t);
+int drf_ctx_get_tuning(drf_ctx *ctx, drf_tuning *t);
 
 /* Library version string. */
 const char *drf_version(void);

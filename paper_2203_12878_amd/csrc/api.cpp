@@ -13,11 +13,19 @@
 //                        LDS sort + segmented scan per tile; buckets of a
 //                        single index value reduce directly
 //   results (GPU)        witness (least phase, index, pair), counts, status
+// Protocols whose planner bound proves every phase fits one LDS tile skip
+// the count pass and the host round trip: their fused units count, sort
+// and scan in one kernel.
+//
+// A prepared batch runs this once while recording every device operation,
+// then captures the recorded sequence into one hipGraph that replays the
+// whole device work (fills are kernels, never memset nodes).
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -38,7 +46,10 @@ struct drf_ctx {
     void *poolB = nullptr;
     size_t sizeB = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t counted = nullptr;
     bool done_valid = false;
+    uint32_t cus = 256;
+    drf_tuning tune = {(uint32_t)drf::TILE, 8, 1u << 12, 1u << 16};
     // per-kernel-class timing
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -49,8 +60,7 @@ struct drf_ctx {
 
 namespace {
 
-constexpr uint64_t ITEM_EVENTS = 1ull << 16;   // target access events per count/emit item
-constexpr uint64_t UNIT_EVENTS = 1ull << 12;   // target access events per fused unit
+
 constexpr uint64_t CAND_CAP = 1ull << 20;      // candidates per launch
 constexpr uint64_t ALIGN = 256;
 
@@ -174,10 +184,62 @@ struct BigPhase {
     uint32_t local;
 };
 
+// Device operations of a recorded call, and the device memory they use.
+struct Recorder {
+    std::vector<std::function<hipError_t(hipStream_t)>> ops;
+    std::vector<void *> owned;     // device allocations kept for the replays
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+
+    void *alloc(size_t bytes) {
+        size_t off = (arena_used + ALIGN - 1) & ~(ALIGN - 1);
+        if (!arena || off + bytes > arena_cap) {
+            const size_t cap = std::max<size_t>(bytes + ALIGN, 64ull << 20);
+            void *p = nullptr;
+            if (hipMalloc(&p, cap) != hipSuccess) {
+                (void)hipGetLastError();
+                throw Fail{DRF_E_NOMEM};
+            }
+            owned.push_back(p);
+            arena = (char *)p;
+            arena_cap = cap;
+            off = 0;
+        }
+        arena_used = off + bytes;
+        return arena + off;
+    }
+};
+
 struct Call {
     drf_ctx *ctx;
     hipStream_t st;
     uint32_t count;
+    Recorder *rec = nullptr;
+
+    // run a device operation on the call's stream (and record it)
+    template <class F>
+    void dev(F f) {
+        hipck(f(st));
+        if (rec) rec->ops.emplace_back(f);
+    }
+    void fill32(void *p, uint32_t word, size_t bytes) {
+        uint32_t *q = (uint32_t *)p;
+        const uint64_t n = bytes / 4;
+        dev([=](hipStream_t s) { return launch_fill_u32(q, word, n, s); });
+    }
+    // upload host data; a recorded call gives every upload its own memory
+    template <class T>
+    T *put(void *region, const std::vector<T> &v) {
+        if (v.empty()) return (T *)region;
+        void *dst = rec ? rec->alloc(v.size() * sizeof(T)) : region;
+        upload(keep, dst, v, st);
+        return (T *)dst;
+    }
+    void sync() {
+        hipck(hipStreamSynchronize(st));
+        keep.clear();
+    }
+
     std::vector<Plan> plans;
     std::vector<int32_t> status;
     std::vector<uint64_t> poff;
@@ -186,12 +248,15 @@ struct Call {
     std::vector<FixedVal> fixed;
     std::vector<uint32_t> code;
     std::vector<Item> items[2];        // narrow, wide
+    std::vector<char> stat;            // phases proven to fit one LDS tile: no count pass
+    std::vector<Unit> sunits[2];       // fused units of those protocols, narrow / wide
     uint64_t item_cnt_words = 0;
     uint64_t total_phases = 0;
     Keep keep;
 
     // pool A offsets
-    size_t o_protos, o_nests, o_fixed, o_code, o_items[2], o_itemcnt, o_ovf, o_best, o_cand, o_units, o_rin, o_res;
+    size_t o_protos, o_nests, o_fixed, o_code, o_items[2], o_itemcnt, o_ovf, o_nrec, o_qhead, o_best, o_cand, o_units,
+        o_sunits[2], o_rin, o_res;
     size_t needA = 0;
 
     void plan_all(const uint32_t *codep, const uint64_t *code_off, const uint32_t *nthreads) {
@@ -212,6 +277,7 @@ struct Call {
 
     void build_blob() {
         status.assign(count, 0);
+        stat.assign(count, 0);
         poff.assign(count, 0);
         protos.assign(count, ProtoDesc{});
         for (uint32_t i = 0; i < count; i++) {
@@ -254,7 +320,18 @@ struct Call {
                 for (auto &f : ne.fixed) fixed.push_back(FixedVal{f.first, 0, f.second});
                 nests.push_back(nd);
                 pd.nnests++;
-                make_items((uint32_t)nests.size() - 1, p.n, p.wide);
+            }
+            stat[i] = p.max_phase_records <= (uint64_t)ctx->tune.tile_events;
+            if (stat[i]) {
+                if (pd.nnests == 0) continue;
+                // units of about unit_events (by the static bound), one phase at least
+                const uint64_t per = std::max<uint64_t>(1, p.max_phase_records);
+                const uint64_t step = std::max<uint64_t>(1, ctx->tune.unit_events / per);
+                for (uint64_t k = 0; k < pd.nphases; k += step)
+                    sunits[pd.wide].push_back(Unit{i, UNIT_STATIC, pd.phase_off + k,
+                                                   pd.phase_off + std::min<uint64_t>(pd.nphases, k + step)});
+            } else {
+                for (uint32_t j = pd.nest0; j < pd.nest0 + pd.nnests; j++) make_items(j, p.n, p.wide);
             }
         }
     }
@@ -264,7 +341,7 @@ struct Call {
         if (n == 0) return;
         const uint64_t lanes = std::min<uint64_t>(n, WG);
         const uint64_t per_iter = lanes * std::max<uint64_t>(1, nd.rec_bound);
-        const uint64_t F = std::max<uint64_t>(1, ITEM_EVENTS / per_iter);
+        const uint64_t F = std::max<uint64_t>(1, ctx->tune.item_events / per_iter);
         const uint32_t nb = (n + WG - 1) / WG;
         for (uint64_t f0 = 0; f0 < nd.iters;) {
             uint64_t f1 = std::min(nd.iters, f0 + F);
@@ -297,49 +374,76 @@ struct Call {
         o_items[1] = b.reserve(items[1].size() * sizeof(Item));
         o_itemcnt = b.reserve(item_cnt_words * sizeof(uint32_t));
         o_ovf = b.reserve(count * sizeof(uint32_t));
+        o_nrec = b.reserve(count * sizeof(uint64_t));
+        o_qhead = b.reserve(64 * sizeof(uint32_t));
         o_best = b.reserve(count * sizeof(Best));
         o_cand = b.reserve(CAND_CAP * sizeof(Cand));
         o_units = b.reserve(std::min<uint64_t>(nunits_max, CAND_CAP) * sizeof(Unit));
+        o_sunits[0] = b.reserve(sunits[0].size() * sizeof(Unit));
+        o_sunits[1] = b.reserve(sunits[1].size() * sizeof(Unit));
         o_rin = b.reserve(count * sizeof(ResultIn));
         o_res = b.used;
         needA = b.used + ALIGN;
     }
 };
 
-// One wave of big phases [bi, be) of the global big-phase list, holding
-// `recs` records in total: emit, then partition levels until every bucket
-// fits an LDS tile (or holds a single index value).
-void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, uint64_t recs, Best *best,
-              Cand *cand) {
+// Layout of pool B for one wave of `recs` big-phase records over a window
+// of win_n phases.
+struct WaveLayout {
+    size_t o_bb, o_cur, o_ra, o_rb, o_hist, o_starts, o_segs, o_chunks, o_tiles, o_groups, o_acc, o_wi0, o_wi1;
+    size_t bytes;
+    uint64_t hist_max, nsegs_max, chunks_max;
+    uint32_t sstride;
+};
+
+WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t nitems0, uint64_t nitems1,
+                       uint32_t tile, uint32_t dbits) {
+    WaveLayout L{};
+    L.nsegs_max = recs / tile + 1;
+    L.chunks_max = recs / CHUNK + L.nsegs_max + 1;
+    L.hist_max = L.chunks_max << dbits;
+    const uint64_t tiles_max = std::min<uint64_t>(L.nsegs_max << dbits, recs) + 1;
+    L.sstride = 1u << dbits;
+    Bump b;
+    L.o_bb = b.reserve(win_n * 8);
+    L.o_cur = b.reserve(win_n * 8);
+    L.o_ra = b.reserve(recs * 8);
+    L.o_rb = b.reserve(recs * 8);
+    L.o_hist = b.reserve((L.hist_max + scan_tmp_words(L.hist_max)) * 8);
+    L.o_starts = b.reserve(L.nsegs_max * L.sstride * 8);
+    L.o_segs = b.reserve(L.nsegs_max * sizeof(Seg));
+    L.o_chunks = b.reserve(L.chunks_max * sizeof(Chunk));
+    L.o_tiles = b.reserve(std::min<uint64_t>(tiles_max, CAND_CAP) * sizeof(Tile));
+    L.o_groups = b.reserve(std::min<uint64_t>(L.nsegs_max + nbig, CAND_CAP) * sizeof(Group));
+    L.o_acc = b.reserve(std::min<uint64_t>(L.nsegs_max + nbig, CAND_CAP) * sizeof(SingleAcc));
+    L.o_wi0 = b.reserve(nitems0 * sizeof(Item));
+    L.o_wi1 = b.reserve(nitems1 * sizeof(Item));
+    L.bytes = b.used + ALIGN;
+    return L;
+}
+
+struct Wave {
+    size_t bi, be;
+    uint64_t recs;
+    std::vector<Item> witems[2];
+};
+
+// One wave of big phases [bi, be) of the global big-phase list: emit, then
+// partition levels until every bucket fits an LDS tile (or holds a single
+// index value).  Pool B has been sized for the largest wave.
+void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *best, Cand *cand) {
     drf_ctx *ctx = C.ctx;
     hipStream_t st = C.st;
     void *A = ctx->poolA;
+    void *B = ctx->poolB;
+    const size_t bi = W.bi, be = W.be;
+    const uint64_t recs = W.recs;
     const uint64_t win_lo = big[bi].k;
     const uint64_t win_n = big[be - 1].k - win_lo + 1;
-
-    std::vector<Item> witems[2];
-    for (int w = 0; w < 2; w++)
-        for (const Item &it : C.items[w])
-            if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) witems[w].push_back(it);
-
-    const uint64_t nsegs_max = recs / TILE + 1;
-    const uint64_t chunks_max = recs / CHUNK + nsegs_max + 1;
-    const uint64_t hist_max = chunks_max * RADIX;
-    const uint64_t tiles_max = std::min<uint64_t>(nsegs_max * RADIX, recs) + 1;
-    Bump b;
-    const size_t o_bb = b.reserve(win_n * 8), o_cur = b.reserve(win_n * 8);
-    const size_t o_ra = b.reserve(recs * 8), o_rb = b.reserve(recs * 8);
-    const size_t o_hist = b.reserve((hist_max + scan_tmp_words(hist_max)) * 8);
-    const size_t o_starts = b.reserve(nsegs_max * RADIX * 8);
-    const size_t o_segs = b.reserve(nsegs_max * sizeof(Seg));
-    const size_t o_chunks = b.reserve(chunks_max * sizeof(Chunk));
-    const size_t o_tiles = b.reserve(std::min<uint64_t>(tiles_max, CAND_CAP) * sizeof(Tile));
-    const size_t o_groups = b.reserve(std::min<uint64_t>(nsegs_max + (be - bi), CAND_CAP) * sizeof(Group));
-    const size_t o_acc = b.reserve(std::min<uint64_t>(nsegs_max + (be - bi), CAND_CAP) * sizeof(SingleAcc));
-    const size_t o_wi0 = b.reserve(witems[0].size() * sizeof(Item));
-    const size_t o_wi1 = b.reserve(witems[1].size() * sizeof(Item));
-    grow(ctx->poolB, ctx->sizeB, b.used + ALIGN);
-    void *B = ctx->poolB;
+    const uint32_t tile = ctx->tune.tile_events;
+    const uint32_t dbits = ctx->tune.digit_bits;
+    const WaveLayout L = wave_layout(recs, win_n, be - bi, W.witems[0].size(), W.witems[1].size(), tile, dbits);
+    const uint32_t sstride = L.sstride;
 
     // ---- emit the wave's records, phase-major
     std::vector<unsigned long long> bb(win_n, ~0ull);
@@ -350,21 +454,27 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
         pos[j - bi] = p;
         p += big[j].count;
     }
-    upload(C.keep, at<void>(B, o_bb), bb, st);
-    hipck(hipMemsetAsync(at<void>(B, o_cur), 0, win_n * 8, st));
-    upload(C.keep, at<void>(B, o_wi0), witems[0], st);
-    upload(C.keep, at<void>(B, o_wi1), witems[1], st);
-    unsigned long long *in = at<unsigned long long>(B, o_ra), *out = at<unsigned long long>(B, o_rb);
-    const size_t o_wi[2] = {o_wi0, o_wi1};
+    const unsigned long long *dbb = C.put(at<void>(B, L.o_bb), bb);
+    unsigned long long *dcur = at<unsigned long long>(B, L.o_cur);
+    C.fill32(dcur, 0, win_n * 8);
+    const Item *dwi[2] = {C.put(at<void>(B, L.o_wi0), W.witems[0]), C.put(at<void>(B, L.o_wi1), W.witems[1])};
+    unsigned long long *in = at<unsigned long long>(B, L.o_ra), *out = at<unsigned long long>(B, L.o_rb);
+    const NestDesc *dnests = at<NestDesc>(A, C.o_nests);
+    const ProtoDesc *dprotos = at<ProtoDesc>(A, C.o_protos);
+    const FixedVal *dfixed = at<FixedVal>(A, C.o_fixed);
+    const uint32_t *dcode = at<uint32_t>(A, C.o_code);
+    const uint32_t *ditemcnt = at<uint32_t>(A, C.o_itemcnt);
     for (int w = 0; w < 2; w++) {
-        const Item *it = at<Item>(B, o_wi[w]);
-        for (uint64_t s0 = 0; s0 < witems[w].size(); s0 += 1u << 30) {
-            const uint32_t n = (uint32_t)std::min<uint64_t>(witems[w].size() - s0, 1u << 30);
+        const Item *it = dwi[w];
+        for (uint64_t s0 = 0; s0 < W.witems[w].size(); s0 += 1u << 30) {
+            const uint32_t n = (uint32_t)std::min<uint64_t>(W.witems[w].size() - s0, 1u << 30);
+            const bool wide = w == 1;
+            unsigned long long *recbuf = in;
             Prof pr(ctx, st, K_EMIT, w == 0 ? recs : 0, w == 0 ? recs * 8 : 0);
-            hipck(launch_emit(it + s0, n, w == 1, at<NestDesc>(A, C.o_nests), at<ProtoDesc>(A, C.o_protos),
-                              at<FixedVal>(A, C.o_fixed), at<uint32_t>(A, C.o_code), at<uint32_t>(A, C.o_itemcnt),
-                              at<unsigned long long>(B, o_bb), at<unsigned long long>(B, o_cur), win_lo, win_n, in,
-                              recs, st));
+            C.dev([=](hipStream_t s) {
+                return launch_emit(it + s0, n, wide, dnests, dprotos, dfixed, dcode, ditemcnt, dbb, dcur, win_lo,
+                                   win_n, recbuf, recs, s);
+            });
         }
     }
 
@@ -372,40 +482,38 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
         for (uint64_t g0 = 0; g0 < groups.size(); g0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(groups.size() - g0, CAND_CAP);
             std::vector<Group> part(groups.begin() + g0, groups.begin() + g0 + n);
-            std::vector<SingleAcc> acc(n, SingleAcc{NONE32, NONE32, 0, NONE32});
-            upload(C.keep, at<void>(B, o_groups), part, st);
-            upload(C.keep, at<void>(B, o_acc), acc, st);
+            const Group *dg = C.put(at<void>(B, L.o_groups), part);
+            SingleAcc *dacc = C.rec ? (SingleAcc *)C.rec->alloc(n * sizeof(SingleAcc)) : at<SingleAcc>(B, L.o_acc);
+            C.dev([=](hipStream_t s) { return launch_init_acc(dacc, (uint32_t)n, s); });
             uint64_t gl = 0;
             for (auto &g : part) gl += g.len;
             {
                 Prof pr(ctx, st, K_SINGLE, gl, gl * 16);
-                hipck(launch_single(at<Group>(B, o_groups), (uint32_t)n, recbuf, at<SingleAcc>(B, o_acc), cand, best,
-                                    st));
+                C.dev([=](hipStream_t s) { return launch_single(dg, (uint32_t)n, recbuf, dacc, cand, best, s); });
             }
             {
                 Prof pr(ctx, st, K_OTHER, 0, 0);
-                hipck(launch_pick(cand, n, best, st));
+                C.dev([=](hipStream_t s) { return launch_pick(cand, n, best, s); });
             }
-            hipck(hipStreamSynchronize(st));
-            C.keep.clear();
+            C.sync();
         }
     };
     auto run_tiles = [&](const std::vector<Tile> &tiles, const unsigned long long *recbuf) {
         for (uint64_t t0 = 0; t0 < tiles.size(); t0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(tiles.size() - t0, CAND_CAP);
             std::vector<Tile> part(tiles.begin() + t0, tiles.begin() + t0 + n);
-            upload(C.keep, at<void>(B, o_tiles), part, st);
+            const Tile *dt = C.put(at<void>(B, L.o_tiles), part);
             uint64_t tl = 0;
             for (auto &t : part) tl += t.len;
             {
                 Prof pr(ctx, st, K_TILE, tl, tl * 8);
-                hipck(launch_tiles(at<Tile>(B, o_tiles), (uint32_t)n, recbuf, cand, best, st));
+                C.dev([=](hipStream_t s) { return launch_tiles(dt, (uint32_t)n, recbuf, cand, best, s); });
             }
             {
                 Prof pr(ctx, st, K_OTHER, 0, 0);
-                hipck(launch_pick(cand, n, best, st));
+                C.dev([=](hipStream_t s) { return launch_pick(cand, n, best, s); });
             }
-            if (t0 + CAND_CAP < tiles.size()) { hipck(hipStreamSynchronize(st)); C.keep.clear(); }
+            if (t0 + CAND_CAP < tiles.size()) C.sync();
         }
     };
 
@@ -423,13 +531,14 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
         sg.len = big[j].count;
         sg.proto = big[j].proto;
         sg.phase = big[j].local;
-        sg.dbits = std::min<uint32_t>(8, r);
+        sg.dbits = std::min<uint32_t>(dbits, r);
         sg.shift = r - sg.dbits;
         segs.push_back(sg);
     }
     if (!groups.empty()) run_groups(groups, in);
 
-    unsigned long long *hist = at<unsigned long long>(B, o_hist);
+    unsigned long long *hist = at<unsigned long long>(B, L.o_hist);
+    unsigned long long *dstarts = at<unsigned long long>(B, L.o_starts);
     while (!segs.empty()) {
         std::vector<Chunk> chunks;
         std::vector<uint64_t> out_start(segs.size());
@@ -443,30 +552,30 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
             op += sg.len;
             for (uint32_t c = 0; c < sg.nchunks; c++) chunks.push_back(Chunk{(uint32_t)s2, c});
         }
-        upload(C.keep, at<void>(B, o_segs), segs, st);
-        upload(C.keep, at<void>(B, o_chunks), chunks, st);
-        const Seg *dsegs = at<Seg>(B, o_segs);
-        const Chunk *dch = at<Chunk>(B, o_chunks);
+        const Seg *dsegs = C.put(at<void>(B, L.o_segs), segs);
+        const Chunk *dch = C.put(at<void>(B, L.o_chunks), chunks);
+        const uint32_t nch = (uint32_t)chunks.size(), nsg = (uint32_t)segs.size();
+        const unsigned long long *cin = in;
+        unsigned long long *cout = out;
         {
             Prof pr(ctx, st, K_HIST, op, op * 8);
-            hipck(launch_hist(dsegs, dch, (uint32_t)chunks.size(), in, hist, st));
+            C.dev([=](hipStream_t s) { return launch_hist(dsegs, dch, nch, cin, hist, s); });
         }
         {
             Prof pr(ctx, st, K_SCAN, 0, hb * 16);
-            hipck(launch_scan_u64(hist, hb, hist + hb, st));
+            C.dev([=](hipStream_t s) { return launch_scan_u64(hist, hb, hist + hb, s); });
         }
         {
             Prof pr(ctx, st, K_SCATTER, op, op * 16);
-            hipck(launch_scatter(dsegs, dch, (uint32_t)chunks.size(), in, hist, out, recs, st));
+            C.dev([=](hipStream_t s) { return launch_scatter(dsegs, dch, nch, cin, hist, cout, recs, s); });
         }
         {
             Prof pr(ctx, st, K_OTHER, 0, 0);
-            hipck(launch_starts(dsegs, (uint32_t)segs.size(), hist, at<unsigned long long>(B, o_starts), st));
+            C.dev([=](hipStream_t s) { return launch_starts(dsegs, nsg, hist, dstarts, sstride, s); });
         }
-        std::vector<uint64_t> starts(segs.size() * RADIX);
-        hipck(hipMemcpyAsync(starts.data(), at<void>(B, o_starts), starts.size() * 8, hipMemcpyDeviceToHost, st));
-        hipck(hipStreamSynchronize(st));
-        C.keep.clear();
+        std::vector<uint64_t> starts(segs.size() * sstride);
+        hipck(hipMemcpyAsync(starts.data(), dstarts, starts.size() * 8, hipMemcpyDeviceToHost, st));
+        C.sync();
 
         std::vector<Seg> next;
         std::vector<Tile> tiles;
@@ -478,30 +587,30 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
             // hold disjoint index values: one tile takes several of them
             Tile cur{0, 0, sg.proto, sg.phase, 0};
             for (uint32_t d = 0; d < nd; d++) {
-                const uint64_t a = starts[s2 * RADIX + d];
-                const uint64_t e = (d + 1 < nd) ? starts[s2 * RADIX + d + 1] : out_start[s2] + sg.len;
-                const uint64_t len = e - a;
+                const uint64_t a0 = starts[s2 * sstride + d];
+                const uint64_t e = (d + 1 < nd) ? starts[s2 * sstride + d + 1] : out_start[s2] + sg.len;
+                const uint64_t len = e - a0;
                 if (len == 0) continue;
-                if (len <= (uint64_t)TILE) {
-                    if (cur.len && cur.start + cur.len == a && cur.len + len <= (uint64_t)TILE) {
+                if (len <= (uint64_t)tile) {
+                    if (cur.len && cur.start + cur.len == a0 && cur.len + len <= (uint64_t)tile) {
                         cur.len += (uint32_t)len;
                     } else {
                         if (cur.len) tiles.push_back(cur);
-                        cur.start = a;
+                        cur.start = a0;
                         cur.len = (uint32_t)len;
                     }
                     continue;
                 }
                 if (cur.len) { tiles.push_back(cur); cur.len = 0; }
                 if (sg.shift == 0) {
-                    g2.push_back(Group{a, len, sg.proto, sg.phase});
+                    g2.push_back(Group{a0, len, sg.proto, sg.phase});
                 } else {
                     Seg ns{};
-                    ns.start = a;
+                    ns.start = a0;
                     ns.len = len;
                     ns.proto = sg.proto;
                     ns.phase = sg.phase;
-                    ns.dbits = std::min<uint32_t>(8, sg.shift);
+                    ns.dbits = std::min<uint32_t>(dbits, sg.shift);
                     ns.shift = sg.shift - ns.dbits;
                     next.push_back(ns);
                 }
@@ -512,20 +621,20 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, size_t bi, size_t be, u
         if (!g2.empty()) run_groups(g2, out);
         segs.swap(next);
         std::swap(in, out);
-        hipck(hipStreamSynchronize(st));
-        C.keep.clear();
+        C.sync();
     }
 }
 
 int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
                uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
-               hipStream_t st) {
+               hipStream_t st, Recorder *rec = nullptr) {
     if (!ctx || !code_off || !nthreads || (count && (!code || !d_results))) return DRF_E_ARG;
     if (count == 0) return DRF_OK;
     Call C;
     C.ctx = ctx;
     C.st = st;
     C.count = count;
+    C.rec = rec;
     try {
         hipck(hipSetDevice(ctx->device));
         if (ctx->done_valid) hipck(hipStreamWaitEvent(st, ctx->done, 0));
@@ -540,92 +649,147 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         Best *best = at<Best>(A, C.o_best);
         Cand *cand = at<Cand>(A, C.o_cand);
         uint32_t *ovf = at<uint32_t>(A, C.o_ovf);
-        upload(C.keep, at<void>(A, C.o_protos), C.protos, st);
-        upload(C.keep, at<void>(A, C.o_nests), C.nests, st);
-        upload(C.keep, at<void>(A, C.o_fixed), C.fixed, st);
-        upload(C.keep, at<void>(A, C.o_code), C.code, st);
-        for (int w = 0; w < 2; w++) upload(C.keep, at<void>(A, C.o_items[w]), C.items[w], st);
-        if (C.total_phases) hipck(hipMemsetAsync(phase_counts, 0, C.total_phases * sizeof(uint64_t), st));
-        hipck(hipMemsetAsync(ovf, 0, count * sizeof(uint32_t), st));
-        hipck(hipMemsetAsync(best, 0xFF, count * sizeof(Best), st));
-        const ProtoDesc *dprotos = at<ProtoDesc>(A, C.o_protos);
-        const NestDesc *dnests = at<NestDesc>(A, C.o_nests);
-        const FixedVal *dfixed = at<FixedVal>(A, C.o_fixed);
-        const uint32_t *dcode = at<uint32_t>(A, C.o_code);
+        const ProtoDesc *dprotos = C.put(at<void>(A, C.o_protos), C.protos);
+        const NestDesc *dnests = C.put(at<void>(A, C.o_nests), C.nests);
+        const FixedVal *dfixed = C.put(at<void>(A, C.o_fixed), C.fixed);
+        const uint32_t *dcode = C.put(at<void>(A, C.o_code), C.code);
+        const Item *ditems[2] = {C.put(at<void>(A, C.o_items[0]), C.items[0]),
+                                 C.put(at<void>(A, C.o_items[1]), C.items[1])};
+        // the emit pass reads the blob through pool A offsets
+        if (rec) {
+            // recorded calls keep the blob at its pool A offsets too (the
+            // wave code addresses it there); pool A belongs to the recording
+            upload(C.keep, at<void>(A, C.o_protos), C.protos, st);
+            upload(C.keep, at<void>(A, C.o_nests), C.nests, st);
+            upload(C.keep, at<void>(A, C.o_fixed), C.fixed, st);
+            upload(C.keep, at<void>(A, C.o_code), C.code, st);
+        }
+        if (C.total_phases) C.fill32(phase_counts, 0, C.total_phases * sizeof(uint64_t));
+        C.fill32(ovf, 0, count * sizeof(uint32_t));
+        C.fill32(best, 0xFFFFFFFFu, count * sizeof(Best));
         uint32_t *item_cnt = at<uint32_t>(A, C.o_itemcnt);
+        unsigned long long *nrec_dev = at<unsigned long long>(A, C.o_nrec);
+        uint32_t *qhead = at<uint32_t>(A, C.o_qhead);
+        C.fill32(nrec_dev, 0, count * sizeof(uint64_t));
+        C.fill32(qhead, 0, 64 * sizeof(uint32_t));
+        const uint32_t fgrid = ctx->cus * 2;
+        const uint32_t tile = ctx->tune.tile_events;
+        int qslot = 0;
 
-        // ---- count pass
+        // fused launches (persistent, units largest first), pair pick after each
+        auto fused = [&](std::vector<Unit> &units, bool wide, size_t dst_off, const std::vector<uint64_t> &work,
+                         uint64_t events) {
+            if (units.empty()) return;
+            std::vector<size_t> order(units.size());
+            for (size_t i = 0; i < order.size(); i++) order[i] = i;
+            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+            for (uint64_t b0 = 0; b0 < units.size(); b0 += CAND_CAP) {
+                const uint64_t n = std::min<uint64_t>(units.size() - b0, CAND_CAP);
+                std::vector<Unit> part(n);
+                for (uint64_t j = 0; j < n; j++) part[j] = units[order[b0 + j]];
+                const Unit *du = C.put(at<void>(A, dst_off), part);
+                if (qslot >= 64) {
+                    C.fill32(qhead, 0, 64 * sizeof(uint32_t));
+                    qslot = 0;
+                }
+                uint32_t *qh = qhead + qslot++;
+                {
+                    Prof pr(ctx, st, K_FUSED, events, 0);
+                    events = 0;
+                    C.dev([=](hipStream_t s) {
+                        return launch_fused(du, (uint32_t)n, qh, wide, dnests, dprotos, dfixed, dcode, phase_counts,
+                                            nrec_dev, ovf, cand, best, fgrid, tile, s);
+                    });
+                }
+                {
+                    Prof pr(ctx, st, K_OTHER, 0, 0);
+                    C.dev([=](hipStream_t s) { return launch_pick(cand, n, best, s); });
+                }
+                if (b0 + CAND_CAP < units.size()) C.sync();
+            }
+        };
+
+        // ---- count pass (protocols whose phases are not proven small)
+        bool dynamic = false;
+        for (uint32_t i = 0; i < count; i++) dynamic |= (C.status[i] == 0 && !C.stat[i]);
         for (int w = 0; w < 2; w++) {
-            const Item *it = at<Item>(A, C.o_items[w]);
-            for (uint64_t b = 0; b < C.items[w].size(); b += 1u << 30) {
-                uint32_t n = (uint32_t)std::min<uint64_t>(C.items[w].size() - b, 1u << 30);
+            const Item *it = ditems[w];
+            for (uint64_t b0 = 0; b0 < C.items[w].size(); b0 += 1u << 30) {
+                const uint32_t n = (uint32_t)std::min<uint64_t>(C.items[w].size() - b0, 1u << 30);
+                const bool wide = w == 1;
                 Prof pr(ctx, st, K_COUNT, 0, 0);
-                hipck(launch_count(it + b, n, w == 1, dnests, dprotos, dfixed, dcode, phase_counts, item_cnt, ovf, st));
+                C.dev([=](hipStream_t s) {
+                    return launch_count(it + b0, n, wide, dnests, dprotos, dfixed, dcode, phase_counts, item_cnt,
+                                        ovf, s);
+                });
             }
         }
         std::vector<uint64_t> counts(C.total_phases);
         std::vector<uint32_t> hovf(count);
-        if (C.total_phases)
-            hipck(hipMemcpyAsync(counts.data(), phase_counts, C.total_phases * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        hipck(hipMemcpyAsync(hovf.data(), ovf, count * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        hipck(hipStreamSynchronize(st));
-        C.keep.clear();
+        if (dynamic) {
+            if (C.total_phases)
+                hipck(hipMemcpyAsync(counts.data(), phase_counts, C.total_phases * sizeof(uint64_t),
+                                     hipMemcpyDeviceToHost, st));
+            hipck(hipMemcpyAsync(hovf.data(), ovf, count * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            if (!ctx->counted) hipck(hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming));
+            hipck(hipEventRecord(ctx->counted, st));
+        }
 
-        // ---- classification
+        // ---- fused path of protocols proven small: no host round trip;
+        // runs on the device while the host classifies the counted ones
+        for (int w = 0; w < 2; w++) {
+            std::vector<uint64_t> work(C.sunits[w].size());
+            for (size_t j = 0; j < work.size(); j++) {
+                const Unit &u = C.sunits[w][j];
+                work[j] = (u.k1 - u.k0) * C.plans[u.proto].max_phase_records;
+            }
+            fused(C.sunits[w], w == 1, C.o_sunits[w], work, 0);
+        }
+
+        // ---- classification of the counted protocols
         std::vector<uint64_t> nrec(count, 0);
         std::vector<Unit> units[2];
         std::vector<BigPhase> big;
-        for (uint32_t i = 0; i < count; i++) {
-            if (C.status[i]) continue;
-            if (hovf[i]) { C.status[i] = DRF_E_RANGE; continue; }
-            const ProtoDesc &pd = C.protos[i];
-            uint64_t acc = 0, ustart = ~0ull, last_small = 0;
-            for (uint64_t k = pd.phase_off; k < pd.phase_off + pd.nphases; k++) {
-                const uint64_t c = counts[k];
-                nrec[i] += c;
-                if (c == 0) continue;
-                if (c > (uint64_t)TILE) {
-                    big.push_back(BigPhase{k, c, i, (uint32_t)(k - pd.phase_off)});
-                    continue;
+        if (dynamic) {
+            hipck(hipEventSynchronize(ctx->counted));
+            for (uint32_t i = 0; i < count; i++) {
+                if (C.status[i] || C.stat[i]) continue;
+                if (hovf[i]) { C.status[i] = DRF_E_RANGE; continue; }
+                const ProtoDesc &pd = C.protos[i];
+                uint64_t acc = 0, ustart = ~0ull, last_small = 0;
+                for (uint64_t k = pd.phase_off; k < pd.phase_off + pd.nphases; k++) {
+                    const uint64_t c = counts[k];
+                    nrec[i] += c;
+                    if (c == 0) continue;
+                    if (c > (uint64_t)tile) {
+                        big.push_back(BigPhase{k, c, i, (uint32_t)(k - pd.phase_off)});
+                        continue;
+                    }
+                    if (ustart == ~0ull) ustart = k;
+                    last_small = k;
+                    acc += c;
+                    if (acc >= ctx->tune.unit_events) {
+                        units[pd.wide].push_back(Unit{i, 0, ustart, k + 1});
+                        ustart = ~0ull;
+                        acc = 0;
+                    }
                 }
-                if (ustart == ~0ull) ustart = k;
-                last_small = k;
-                acc += c;
-                if (acc >= UNIT_EVENTS) {
-                    units[pd.wide].push_back(Unit{i, 0, ustart, k + 1});
-                    ustart = ~0ull;
-                    acc = 0;
-                }
+                if (ustart != ~0ull) units[pd.wide].push_back(Unit{i, 0, ustart, last_small + 1});
             }
-            if (ustart != ~0ull) units[pd.wide].push_back(Unit{i, 0, ustart, last_small + 1});
-        }
-
-        if (ctx->prof) {
-            uint64_t tot = 0;
-            for (uint32_t i = 0; i < count; i++) tot += nrec[i];
-            for (auto &p : ctx->pending) if (p.cls == K_COUNT) { p.records = tot; break; }
-        }
-
-        // ---- fused path
-        for (int w = 0; w < 2; w++) {
-            for (uint64_t b = 0; b < units[w].size(); b += CAND_CAP) {
-                const uint64_t n = std::min<uint64_t>(units[w].size() - b, CAND_CAP);
-                std::vector<Unit> part(units[w].begin() + b, units[w].begin() + b + n);
-                upload(C.keep, at<void>(A, C.o_units), part, st);
+            if (ctx->prof) {
+                uint64_t tot = 0;
+                for (uint32_t i = 0; i < count; i++) tot += nrec[i];
+                for (auto &pp : ctx->pending) if (pp.cls == K_COUNT) { pp.records = tot; break; }
+            }
+            for (int w = 0; w < 2; w++) {
+                std::vector<uint64_t> work(units[w].size());
                 uint64_t ev = 0;
-                for (uint64_t u = b; u < b + n; u++)
-                    for (uint64_t k = units[w][u].k0; k < units[w][u].k1; k++)
-                        if (counts[k] <= (uint64_t)TILE) ev += counts[k];
-                {
-                    Prof pr(ctx, st, K_FUSED, ev, 0);
-                    hipck(launch_fused(at<Unit>(A, C.o_units), (uint32_t)n, w == 1, dnests, dprotos, dfixed, dcode,
-                                       phase_counts, cand, best, st));
+                for (size_t j = 0; j < work.size(); j++) {
+                    for (uint64_t k = units[w][j].k0; k < units[w][j].k1; k++)
+                        if (counts[k] <= (uint64_t)tile) work[j] += counts[k];
+                    ev += work[j];
                 }
-                {
-                    Prof pr(ctx, st, K_OTHER, 0, 0);
-                    hipck(launch_pick(cand, n, best, st));
-                }
-                if (b + CAND_CAP < units[w].size()) { hipck(hipStreamSynchronize(st)); C.keep.clear(); }
+                fused(units[w], w == 1, C.o_units, work, ev);
             }
         }
 
@@ -634,24 +798,39 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             const uint64_t budget = ctx->limit > C.needA ? ctx->limit - C.needA : 0;
             const uint64_t per_rec = 20;   // two record buffers + partition metadata
             const uint64_t rec_cap = budget / per_rec;
+            std::vector<Wave> waves;
             size_t bi = 0;
             while (bi < big.size()) {
-                // skip phases that can never fit
-                if (big[bi].count > rec_cap) {
+                if (big[bi].count > rec_cap) {   // a phase that can never fit
                     C.status[big[bi].proto] = DRF_E_NOMEM;
                     bi++;
                     continue;
                 }
+                Wave W;
+                W.bi = bi;
+                W.recs = 0;
                 size_t be = bi;
-                uint64_t recs = 0;
-                while (be < big.size() && big[be].count <= rec_cap && recs + big[be].count <= rec_cap &&
+                while (be < big.size() && big[be].count <= rec_cap && W.recs + big[be].count <= rec_cap &&
                        big[be].k - big[bi].k < (1ull << 26)) {
-                    recs += big[be].count;
+                    W.recs += big[be].count;
                     be++;
                 }
-                run_wave(C, big, bi, be, recs, best, cand);
+                W.be = be;
+                const uint64_t win_lo = big[bi].k, win_n = big[be - 1].k - win_lo + 1;
+                for (int w = 0; w < 2; w++)
+                    for (const Item &it : C.items[w])
+                        if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) W.witems[w].push_back(it);
+                waves.push_back(std::move(W));
                 bi = be;
             }
+            size_t needB = 0;
+            for (const Wave &W : waves) {
+                const uint64_t win_n = big[W.be - 1].k - big[W.bi].k + 1;
+                needB = std::max(needB, wave_layout(W.recs, win_n, W.be - W.bi, W.witems[0].size(),
+                                                    W.witems[1].size(), tile, ctx->tune.digit_bits).bytes);
+            }
+            grow(ctx->poolB, ctx->sizeB, needB);
+            for (const Wave &W : waves) run_wave(C, big, W, best, cand);
         }
 
         // ---- results
@@ -660,11 +839,13 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             rin[i].status = C.status[i];
             rin[i].num_phases = C.status[i] ? 0 : (uint32_t)C.protos[i].nphases;
             rin[i].num_records = C.status[i] ? 0 : nrec[i];
+            rin[i].flags = (C.status[i] == 0 && C.stat[i]) ? RESULT_FROM_DEVICE : 0;
         }
-        upload(C.keep, at<void>(A, C.o_rin), rin, st);
+        const ResultIn *drin = C.put(at<void>(A, C.o_rin), rin);
         {
             Prof pr(ctx, st, K_OTHER, 0, 0);
-            hipck(launch_result(count, at<ResultIn>(A, C.o_rin), best, (drf_result_dev *)d_results, st));
+            drf_result_dev *dres = (drf_result_dev *)d_results;
+            C.dev([=](hipStream_t s) { return launch_result(count, drin, best, nrec_dev, ovf, dres, s); });
         }
         if (!ctx->done) hipck(hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming));
         hipck(hipEventRecord(ctx->done, st));
@@ -714,6 +895,7 @@ int drf_plan_protocol(const uint32_t *code, uint32_t words, uint32_t num_threads
         out->wide = p.wide ? 1 : 0;
         out->max_records = p.max_records;
         out->nests = p.nests.size();
+        out->max_phase_records = p.max_phase_records;
     }
     return DRF_OK;
 }
@@ -735,6 +917,9 @@ int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out) 
         scratch_limit_bytes = fr / 4 * 3;
     }
     c->limit = scratch_limit_bytes;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+        c->cus = (uint32_t)cus;
     *out = c;
     return DRF_OK;
 }
@@ -746,6 +931,7 @@ int drf_ctx_destroy(drf_ctx *ctx) {
     if (ctx->poolA) (void)hipFree(ctx->poolA);
     if (ctx->poolB) (void)hipFree(ctx->poolB);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
+    if (ctx->counted) (void)hipEventDestroy(ctx->counted);
     for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     delete ctx;
@@ -755,6 +941,33 @@ int drf_ctx_destroy(drf_ctx *ctx) {
 int drf_ctx_set_profiling(drf_ctx *ctx, int on) {
     if (!ctx) return DRF_E_ARG;
     ctx->prof = on != 0;
+    return DRF_OK;
+}
+
+int drf_ctx_set_tuning(drf_ctx *ctx, const drf_tuning *t) {
+    if (!ctx || !t) return DRF_E_ARG;
+    drf_tuning n = ctx->tune;
+    if (t->tile_events) {
+        if (t->tile_events < 256 || t->tile_events > (uint32_t)TILE || (t->tile_events & (t->tile_events - 1)))
+            return DRF_E_ARG;
+        n.tile_events = t->tile_events;
+    }
+    if (t->digit_bits) {
+        if (t->digit_bits < 4 || t->digit_bits > 10) return DRF_E_ARG;
+        n.digit_bits = t->digit_bits;
+    }
+    if (t->unit_events) n.unit_events = t->unit_events;
+    if (t->item_events) {
+        if (t->item_events < 256) return DRF_E_ARG;
+        n.item_events = t->item_events;
+    }
+    ctx->tune = n;
+    return DRF_OK;
+}
+
+int drf_ctx_get_tuning(drf_ctx *ctx, drf_tuning *t) {
+    if (!ctx || !t) return DRF_E_ARG;
+    *t = ctx->tune;
     return DRF_OK;
 }
 
@@ -768,6 +981,75 @@ int drf_ctx_kernel_stats(drf_ctx *ctx, drf_kernel_stat *out, uint32_t cap, uint3
     if (reset) memset(ctx->stats, 0, sizeof ctx->stats);
     return DRF_OK;
 }
+
+struct drf_prepared {
+    drf_ctx *priv = nullptr;       // private context: its pools belong to the recording
+    Recorder rec;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int drf_prepared_destroy(drf_prepared *p) {
+    if (!p) return DRF_E_ARG;
+    if (p->priv) (void)hipSetDevice(p->priv->device);
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (void *q : p->rec.owned) (void)hipFree(q);
+    if (p->priv) drf_ctx_destroy(p->priv);
+    delete p;
+    return DRF_OK;
+}
+
+int drf_prepare_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                      uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
+                      void *stream, drf_prepared **out) {
+    if (!ctx || !out) return DRF_E_ARG;
+    *out = nullptr;
+    drf_prepared *p = new drf_prepared();
+    p->priv = new drf_ctx();
+    p->priv->device = ctx->device;
+    p->priv->limit = ctx->limit;
+    p->priv->tune = ctx->tune;
+    p->priv->cus = ctx->cus;
+    int rc = check_impl(p->priv, code, code_off, nthreads, count, d_results, d_phase_counts, phase_cap,
+                        (hipStream_t)stream, &p->rec);
+    if (rc != DRF_OK) {
+        drf_prepared_destroy(p);
+        return rc;
+    }
+    hipStream_t cs = nullptr;
+    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        for (auto &op : p->rec.ops)
+            if (op(cs) != hipSuccess) ok = false;
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(cs, &g) != hipSuccess) ok = false;
+        p->graph = g;
+    }
+    ok = ok && p->graph && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!ok) {
+        (void)hipGetLastError();
+        drf_prepared_destroy(p);
+        return DRF_E_HIP;
+    }
+    *out = p;
+    return DRF_OK;
+}
+
+int drf_run_prepared(drf_prepared *p, void *stream) {
+    if (!p || !p->exec) return DRF_E_ARG;
+    if (hipSetDevice(p->priv->device) != hipSuccess) return DRF_E_HIP;
+    if (hipGraphLaunch(p->exec, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return DRF_E_HIP;
+    }
+    return DRF_OK;
+}
+
+uint64_t drf_prepared_launches(const drf_prepared *p) { return p ? p->rec.ops.size() : 0; }
 
 int drf_check_protocol(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads,
                        drf_result *d_result, uint64_t *d_phase_counts, uint64_t phase_cap, void *stream) {

@@ -94,10 +94,15 @@ struct Item {
 };
 
 // Fused work unit: phases [k0, k1) (global ids) of one protocol, each with
-// at most the LDS tile capacity of access events.
+// at most the LDS tile capacity of access events.  With UNIT_STATIC the
+// planner proved the bound (no count pass ran): the unit writes the phase
+// counts, adds its events to the protocol total and flags range overflow.
+// Otherwise the count pass ran and phases above the tile are skipped.
+constexpr uint32_t UNIT_STATIC = 1;
+
 struct Unit {
     uint32_t proto;
-    uint32_t pad;
+    uint32_t flags;
     uint64_t k0, k1;
 };
 

@@ -415,6 +415,7 @@ struct Planner {
     uint32_t max_depth = 0;
     std::unordered_map<int, int> code_of_leaf;
     u128 events = 0;
+    u128 phase_events = 0;   // sum over nests of their per-phase maxima
     u128 total_work = 0;
     uint64_t max_index = 0;
 
@@ -839,7 +840,12 @@ struct Planner {
             ne.rec_bound = (uint32_t)std::min<u128>(per, 0xFFFFFFFFu);
             events = sat(events + smul(smul(per, n), it));
             total_work = sat(total_work + smul(smul(sat(work + per + 1), n), it));
+            // iterations sharing one phase: the loops whose body holds no sync
+            u128 same = 1;
+            for (auto &l : ne.loops) if (l.stride == 0) same = smul(same, l.trip);
+            phase_events = sat(phase_events + smul(smul(per, n), same));
         }
+        plan.max_phase_records = (uint64_t)std::min<u128>(phase_events, ~0ull);
         if (events >= MAX_EVENTS || total_work >= MAX_EVENTS * 4) { fail(DRF_E_LIMIT); return; }
         plan.max_records = (uint64_t)events;
         plan.wide = iv_max >= (u128)(1ull << 32);

@@ -67,6 +67,7 @@ struct Plan {
     uint32_t index_bits = 0;
     bool wide = false;
     uint64_t max_records = 0;
+    uint64_t max_phase_records = 0;   // static bound on the events of one phase
     std::vector<Nest> nests;
     // leaf code: leaf statement index -> words
     std::vector<int> leaf_ids;

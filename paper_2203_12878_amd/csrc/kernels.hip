@@ -674,58 +674,91 @@ struct FusedSink {
 };
 
 template <typename T, bool WIDE>
-__global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, const NestDesc *__restrict__ nests,
+__global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, uint32_t nunits,
+                                               uint32_t *__restrict__ qhead, const NestDesc *__restrict__ nests,
                                                const ProtoDesc *__restrict__ protos,
                                                const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
-                                               const unsigned long long *__restrict__ phase_counts,
-                                               Cand *__restrict__ cands, Best *__restrict__ best) {
+                                               unsigned long long *__restrict__ phase_counts,
+                                               unsigned long long *__restrict__ nrec, uint32_t *__restrict__ ovf_flags,
+                                               Cand *__restrict__ cands, Best *__restrict__ best, uint32_t tile) {
     __shared__ unsigned long long lds_rec[TILE];
     __shared__ uint32_t lds_n;
     __shared__ uint32_t lds_res[16];
-    const Unit u = units[blockIdx.x];
-    const ProtoDesc pd = protos[u.proto];
-    Cand *my = &cands[blockIdx.x];
-    if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = u.proto; }
-    bool have = false;
-    for (uint64_t k = u.k0; k < u.k1; k++) {
-        const unsigned long long cnt_k = phase_counts[k];
-        if (cnt_k == 0 || cnt_k > (unsigned long long)TILE) continue;   // empty or handled in HBM
-        if (threadIdx.x == 0) lds_n = 0;
-        __syncthreads();
-        for (uint32_t ni = 0; ni < pd.nnests; ni++) {
-            const NestDesc &nd = nests[pd.nest0 + ni];
-            if (k < nd.phase_base || k > nd.phase_last) continue;
-            const uint64_t fa = first_iter_at(nd, k);
-            if (fa >= nd.iters) continue;
-            T vars[MAXSLOTS];
-            for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
-            load_fixed<T>(nd, fixed, vars);
-            Odo<T> odo;
-            odo.start(nd, fa, vars);
-            const uint32_t *leaf = code + nd.code_off;
-            for (uint64_t f = fa; f < nd.iters && odo.phase == k; f++) {
-                for (uint32_t t0 = 0; t0 < pd.n; t0 += WG) {
-                    const uint32_t tid = t0 + threadIdx.x;
-                    FusedSink sink{lds_rec, &lds_n, tid};
-                    bool ovf = false;
-                    run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
-                }
-                odo.next(nd, vars);
-            }
+    __shared__ uint32_t lds_unit;
+    __shared__ uint32_t lds_ovf;
+    // persistent: workgroups pull units (largest first) from a device queue
+    for (;;) {
+        if (threadIdx.x == 0) {
+            lds_unit = atomicAdd(qhead, 1u);
+            lds_ovf = 0;
         }
         __syncthreads();
-        uint32_t cnt = lds_n;
-        if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: counted above
-        uint32_t npow = 256;
-        while (npow < cnt) npow <<= 1;
-        for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[i] = ~0ull;
-        __syncthreads();
-        block_sort(lds_rec, npow);
-        uint32_t ridx, r1, r2;
-        const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
-        if (f && !have) {
-            have = true;
-            if (threadIdx.x == 0) offer(best, my, u.proto, (uint32_t)(k - pd.phase_off), ridx, r1, r2);
+        const uint32_t ui = lds_unit;
+        if (ui >= nunits) break;
+        const Unit u = units[ui];
+        const bool stat = (u.flags & UNIT_STATIC) != 0;
+        const ProtoDesc pd = protos[u.proto];
+        Cand *my = &cands[ui];
+        if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = u.proto; }
+        bool have = false;
+        unsigned long long total = 0;
+        bool ovf = false;
+        for (uint64_t k = u.k0; k < u.k1; k++) {
+            if (!stat) {
+                const unsigned long long cnt_k = phase_counts[k];
+                if (cnt_k == 0 || cnt_k > (unsigned long long)tile) continue;   // empty or handled in HBM
+            }
+            if (threadIdx.x == 0) lds_n = 0;
+            __syncthreads();
+            for (uint32_t ni = 0; ni < pd.nnests; ni++) {
+                const NestDesc &nd = nests[pd.nest0 + ni];
+                if (k < nd.phase_base || k > nd.phase_last) continue;
+                const uint64_t fa = first_iter_at(nd, k);
+                if (fa >= nd.iters) continue;
+                T vars[MAXSLOTS];
+                for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+                load_fixed<T>(nd, fixed, vars);
+                Odo<T> odo;
+                odo.start(nd, fa, vars);
+                const uint32_t *leaf = code + nd.code_off;
+                for (uint64_t f = fa; f < nd.iters && odo.phase == k; f++) {
+                    for (uint32_t t0 = 0; t0 < pd.n; t0 += WG) {
+                        const uint32_t tid = t0 + threadIdx.x;
+                        FusedSink sink{lds_rec, &lds_n, tid};
+                        run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
+                    }
+                    odo.next(nd, vars);
+                }
+            }
+            __syncthreads();
+            uint32_t cnt = lds_n;
+            if (stat && threadIdx.x == 0) phase_counts[k] = cnt;
+            total += cnt;
+            if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: bounded by count or plan
+            if (cnt == 0) {
+                __syncthreads();
+                continue;
+            }
+            uint32_t npow = 256;
+            while (npow < cnt) npow <<= 1;
+            for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[i] = ~0ull;
+            __syncthreads();
+            block_sort(lds_rec, npow);
+            uint32_t ridx, r1, r2;
+            const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
+            if (f && !have) {
+                have = true;
+                if (threadIdx.x == 0) offer(best, my, u.proto, (uint32_t)(k - pd.phase_off), ridx, r1, r2);
+            }
+            __syncthreads();
+        }
+        if (stat) {
+            if (ballot(ovf) != 0 && lane_id() == 0) atomicOr(&lds_ovf, 1u);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                atomicAdd(&nrec[u.proto], total);
+                if (lds_ovf) atomicOr(&ovf_flags[u.proto], 1u);
+            }
         }
         __syncthreads();
     }
@@ -779,13 +812,13 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
 // starts[s * 256 + d] = first output position of digit d of segment s
 // (the end of the last digit is the end of the segment's output).
 __global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const unsigned long long *__restrict__ offs,
-                         unsigned long long *__restrict__ starts) {
+                         unsigned long long *__restrict__ starts, uint32_t stride) {
     const uint32_t s = blockIdx.x;
     if (s >= nsegs) return;
     const Seg sg = segs[s];
     const uint32_t nd = 1u << sg.dbits;
     for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x)
-        starts[(uint64_t)s * RADIX + d] = offs[sg.hbase + (uint64_t)d * sg.nchunks];
+        starts[(uint64_t)s * stride + d] = offs[sg.hbase + (uint64_t)d * sg.nchunks];
 }
 
 // ================================================================== tiles
@@ -879,10 +912,15 @@ __global__ void k_pick(const Cand *__restrict__ cands, uint64_t n, Best *__restr
 
 // ================================================================ results
 __global__ void k_result(uint32_t count, const ResultIn *__restrict__ rin, const Best *__restrict__ best,
+                         const unsigned long long *__restrict__ nrec, const uint32_t *__restrict__ ovf_flags,
                          drf_result_dev *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const ResultIn r = rin[i];
+    ResultIn r = rin[i];
+    if (r.flags & RESULT_FROM_DEVICE) {
+        r.num_records = nrec[i];
+        if (ovf_flags[i]) r.status = -7;   // range overflow found while evaluating
+    }
     drf_result_dev o;
     o.status = r.status;
     o.racy = 0;
@@ -903,6 +941,18 @@ __global__ void k_result(uint32_t count, const ResultIn *__restrict__ rin, const
         }
     }
     out[i] = o;
+}
+
+// ================================================================== fills
+// (graph-safe replacements for memset: kernels, never memset nodes)
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_init_acc(SingleAcc *__restrict__ a, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = SingleAcc{NONE32, NONE32, 0u, NONE32};
 }
 
 // ================================================================== scan
@@ -973,14 +1023,16 @@ hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const Nest
                   big_base, cursor, win_lo, win_n, recs, cap);
 }
 
-hipError_t launch_fused(const Unit *units, uint32_t nunits, bool wide, const NestDesc *nests,
+hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, bool wide, const NestDesc *nests,
                         const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
-                        const unsigned long long *phase_counts, Cand *cands, Best *best, hipStream_t s) {
+                        unsigned long long *phase_counts, unsigned long long *nrec, uint32_t *ovf_flags,
+                        Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s) {
+    const uint32_t g = nunits < grid ? nunits : grid;
     if (wide)
-        return launch(k_fused<uint64_t, true>, dim3(nunits), dim3(WG), s, units, nests, protos, fixed, code,
-                      phase_counts, cands, best);
-    return launch(k_fused<uint32_t, false>, dim3(nunits), dim3(WG), s, units, nests, protos, fixed, code,
-                  phase_counts, cands, best);
+        return launch(k_fused<uint64_t, true>, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed,
+                      code, phase_counts, nrec, ovf_flags, cands, best, tile);
+    return launch(k_fused<uint32_t, false>, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed, code,
+                  phase_counts, nrec, ovf_flags, cands, best, tile);
 }
 
 hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
@@ -1015,8 +1067,8 @@ hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks
 }
 
 hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs, unsigned long long *starts,
-                         hipStream_t s) {
-    return launch(k_starts, dim3(nsegs), dim3(256), s, segs, nsegs, offs, starts);
+                         uint32_t stride, hipStream_t s) {
+    return launch(k_starts, dim3(nsegs), dim3(256), s, segs, nsegs, offs, starts, stride);
 }
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands, Best *best,
@@ -1035,8 +1087,19 @@ hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned l
                   (const SingleAcc *)acc, cands, best);
 }
 
-hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, drf_result_dev *out, hipStream_t s) {
-    return launch(k_result, dim3((count + 255) / 256), dim3(256), s, count, rin, best, out);
+hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, const unsigned long long *nrec,
+                         const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s) {
+    return launch(k_result, dim3((count + 255) / 256), dim3(256), s, count, rin, best, nrec, ovf_flags, out);
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    return launch(k_fill_u32, dim3((uint32_t)(blocks < 4096 ? blocks : 4096)), dim3(256), s, p, v, n);
+}
+
+hipError_t launch_init_acc(SingleAcc *a, uint32_t n, hipStream_t s) {
+    return launch(k_init_acc, dim3((n + 255) / 256), dim3(256), s, a, n);
 }
 
 hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s) {

@@ -11,7 +11,7 @@ constexpr int WG = 256;            // lanes per workgroup of the evaluator kerne
 constexpr int MAXSPAN = 2048;      // phases one count / emit item may cover
 constexpr int TILE = 8192;         // access events one LDS tile holds (64 KiB)
 constexpr int CHUNK = 4096;        // records per partition chunk (one workgroup)
-constexpr int RADIX = 256;         // partition digit: 8 bits
+constexpr int RADIX = 1024;        // largest partition digit: 10 bits (starts stride per segment)
 
 // Big-phase segment being partitioned by its next 8 (or fewer) index bits.
 struct Seg {
@@ -68,9 +68,10 @@ hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const Nest
                        unsigned long long *cursor, uint64_t win_lo, uint64_t win_n, unsigned long long *recs,
                        unsigned long long cap, hipStream_t s);
 
-hipError_t launch_fused(const Unit *units, uint32_t nunits, bool wide, const NestDesc *nests,
+hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, bool wide, const NestDesc *nests,
                         const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
-                        const unsigned long long *phase_counts, Cand *cands, Best *best, hipStream_t s);
+                        unsigned long long *phase_counts, unsigned long long *nrec, uint32_t *ovf_flags,
+                        Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s);
 
 hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
                        unsigned long long *hist, hipStream_t s);
@@ -83,7 +84,7 @@ hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks
                           hipStream_t s);
 
 hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs,
-                         unsigned long long *starts, hipStream_t s);
+                         unsigned long long *starts, uint32_t stride, hipStream_t s);
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands,
                         Best *best, hipStream_t s);
@@ -92,6 +93,8 @@ hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned l
                          SingleAcc *acc, Cand *cands, Best *best, hipStream_t s);
 
 hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_init_acc(SingleAcc *a, uint32_t n, hipStream_t s);
 
 // Final per-protocol result (same layout as drf_result of the C ABI).
 struct drf_result_dev {
@@ -103,12 +106,17 @@ struct drf_result_dev {
     uint32_t reserved;
 };
 
+constexpr uint32_t RESULT_FROM_DEVICE = 1;   // record total and overflow come from the fused path
+
 struct ResultIn {
     int32_t status;
     uint32_t num_phases;
     uint64_t num_records;
+    uint32_t flags;
+    uint32_t pad;
 };
 
-hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, drf_result_dev *out, hipStream_t s);
+hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, const unsigned long long *nrec,
+                         const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s);
 
 }  // namespace drf

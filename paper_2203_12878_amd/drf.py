@@ -34,7 +34,13 @@ class DrfError(RuntimeError):
 
 class Plan(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("num_phases", ctypes.c_uint32), ("index_bits", ctypes.c_uint32),
-                ("wide", ctypes.c_uint32), ("max_records", ctypes.c_uint64), ("nests", ctypes.c_uint64)]
+                ("wide", ctypes.c_uint32), ("max_records", ctypes.c_uint64), ("nests", ctypes.c_uint64),
+                ("max_phase_records", ctypes.c_uint64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_events", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32),
+                ("unit_events", ctypes.c_uint32), ("item_events", ctypes.c_uint32)]
 
 
 class _Result(ctypes.Structure):
@@ -69,8 +75,21 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.drf_check_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.drf_prepare_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        L.drf_run_prepared.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.drf_prepared_destroy.argtypes = [ctypes.c_void_p]
+        L.drf_prepared_launches.argtypes = [ctypes.c_void_p]
+        L.drf_prepared_launches.restype = ctypes.c_uint64
+        for f in ("drf_prepare_batch", "drf_run_prepared", "drf_prepared_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        L.drf_ctx_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
+        L.drf_ctx_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
+        L.drf_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
         for f in ("drf_compile_text", "drf_plan_protocol", "drf_ctx_create", "drf_ctx_destroy",
-                  "drf_check_protocol", "drf_check_batch"):
+                  "drf_check_protocol", "drf_check_batch", "drf_ctx_set_tuning", "drf_ctx_get_tuning",
+                  "drf_ctx_set_profiling"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -125,7 +144,8 @@ class Batch:
     """Bytecode of several protocols packed for drf_check_batch, with the
     device result and phase-count buffers it needs."""
 
-    def __init__(self, items: Sequence[Tuple[Union[str, np.ndarray], int]], device: int = 0):
+    def __init__(self, items: Sequence[Tuple[Union[str, np.ndarray], int]], device: int = 0,
+                 plans: Optional[Sequence[Plan]] = None):
         import torch
         codes = [compile_text(c) if isinstance(c, str) else np.ascontiguousarray(c, dtype=np.uint32)
                  for c, _ in items]
@@ -135,7 +155,7 @@ class Batch:
         if codes:
             self.code_off[1:] = np.cumsum([len(c) for c in codes])
         self.code = np.concatenate(codes).astype(np.uint32) if codes else np.zeros(1, np.uint32)
-        self.plans = [plan(c, int(n)) for c, n in zip(codes, self.nthreads)]
+        self.plans = list(plans) if plans is not None else [plan(c, int(n)) for c, n in zip(codes, self.nthreads)]
         self.phase_off = np.zeros(self.count + 1, dtype=np.uint64)
         nph = [p.num_phases if p.status == 0 else 0 for p in self.plans]
         if nph:
@@ -163,6 +183,41 @@ class Batch:
         return out
 
 
+class Prepared:
+    """A batch checked once and captured as one hipGraph (drf_prepare_batch);
+    run() replays the whole device work into the batch's buffers."""
+
+    def __init__(self, chk: "Checker", b: Batch, stream=None):
+        self.batch = b
+        self._h = ctypes.c_void_p()
+        rc = lib().drf_prepare_batch(chk._ctx, _u32p(b.code), _u64p(b.code_off), _u32p(b.nthreads), b.count,
+                                     ctypes.c_void_p(b.results.data_ptr()), ctypes.c_void_p(b.counts.data_ptr()),
+                                     b.total_phases, chk._stream(stream), ctypes.byref(self._h))
+        if rc != OK:
+            raise DrfError(rc, "drf_prepare_batch")
+        self._stream = chk._stream
+
+    @property
+    def launches(self) -> int:
+        return int(lib().drf_prepared_launches(self._h))
+
+    def run(self, stream=None) -> None:
+        rc = lib().drf_run_prepared(self._h, self._stream(stream))
+        if rc != OK:
+            raise DrfError(rc, "drf_run_prepared")
+
+    def close(self):
+        if self._h:
+            lib().drf_prepared_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Checker:
     """Owns a libdrf context on one HIP device (one per host thread)."""
 
@@ -186,6 +241,17 @@ class Checker:
             self.close()
         except Exception:
             pass
+
+    def set_tuning(self, tile_events=0, digit_bits=0, unit_events=0, item_events=0):
+        t = Tuning(tile_events, digit_bits, unit_events, item_events)
+        rc = lib().drf_ctx_set_tuning(self._ctx, ctypes.byref(t))
+        if rc != OK:
+            raise DrfError(rc, "drf_ctx_set_tuning")
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        lib().drf_ctx_get_tuning(self._ctx, ctypes.byref(t))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
     def _stream(self, stream):
         import torch
@@ -216,6 +282,10 @@ class Checker:
                                       int(b.phase_off[i + 1] - b.phase_off[i]), s)
             if rc != OK:
                 raise DrfError(rc, "drf_check_protocol")
+
+    def prepare(self, b: Batch, stream=None) -> Prepared:
+        """Check `b` once and capture the device work as one hipGraph."""
+        return Prepared(self, b, stream)
 
     def check_batch(self, items: Sequence[Tuple[Union[str, np.ndarray], int]], stream=None) -> List[CheckResult]:
         import torch

@@ -16,13 +16,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     txt = open(os.path.join(ROOT, "include", "drf.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(drf_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|uint64_t|const char \*)\s*(drf_\w+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_declared_symbols():
     L = drf.lib()
     syms = declared_symbols()
-    assert len(syms) >= 7
+    assert len(syms) >= 14
     for s in syms:
         assert hasattr(L, s), s
     assert L.drf_version().startswith(b"libdrf")
