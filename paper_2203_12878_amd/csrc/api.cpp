@@ -291,6 +291,14 @@ struct Call {
             pd.nnests = 0;
             pd.phase_off = total_phases;
             pd.nphases = 0;
+            {
+                uint32_t tb = 0;
+                while (tb < 31 && p.n > 1 && ((uint64_t)(p.n - 1) >> tb) != 0) tb++;
+                pd.tb = tb;
+                pd.ib = p.index_bits;
+                pd.pack = (!p.wide && p.index_bits + tb + 1 <= 48) ? 1 : 0;
+                pd.phase_bound = (uint32_t)std::min<uint64_t>(p.max_phase_records, 0xFFFFFFFFu);
+            }
             if (p.status) continue;
             pd.nphases = p.num_phases;
             total_phases += p.num_phases;
@@ -308,6 +316,10 @@ struct Call {
                 nd.nfixed = (uint32_t)ne.fixed.size();
                 nd.fixed_off = (uint32_t)fixed.size();
                 nd.rec_bound = ne.rec_bound;
+                {
+                    const int g = p.leaf_guard[p.nest_leaf_code[j]];
+                    nd.guard_off = g < 0 ? NONE32 : leaf_off[p.nest_leaf_code[j]] + (uint32_t)g;
+                }
                 nd.iters = ne.iters;
                 nd.phase_base = pd.phase_off + ne.phase_base;
                 nd.phase_last = pd.phase_off + ne.phase_last;

@@ -57,6 +57,13 @@ struct ProtoDesc {
     uint32_t nnests;
     uint64_t phase_off;  // global id of phase 0
     uint64_t nphases;
+    // LDS key layout of the fused path: with `pack`, a record of phase
+    // k0 + r is (r << (ib + tb + 1)) | index << (tb + 1) | tid << 1 | write,
+    // so several phases share one sort; otherwise index << 32 | tid << 1 | w
+    uint32_t tb;         // bits of the largest tid
+    uint32_t ib;         // bits of the largest index
+    uint32_t pack;
+    uint32_t phase_bound;  // static bound on the events of one phase (clipped)
 };
 
 struct NestDesc {
@@ -66,6 +73,9 @@ struct NestDesc {
     uint32_t nfixed;       // host-unrolled enclosing loops: fixed slot values
     uint32_t fixed_off;    // into the fixed (slot, value) table
     uint32_t rec_bound;    // per-lane access events per iteration (upper bound, saturated)
+    uint32_t guard_off;    // thread-limit expression (word offset) or NONE32: only tids below
+                           // its value can access memory in an iteration
+    uint32_t pad2;
     uint64_t iters;        // product of trips (>= 1)
     uint64_t phase_base;   // global phase id of iteration 0
     uint64_t phase_last;   // global phase id of the last iteration

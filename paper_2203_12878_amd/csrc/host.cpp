@@ -813,6 +813,33 @@ struct Planner {
         }
     }
 
+    bool has_access(int si) const {
+        const SNode &s = ir.s[si];
+        if (s.kind == B_ACC) return true;
+        for (int k : s.kids) if (has_access(k)) return true;
+        return false;
+    }
+
+    // A leaf `if (tid < e) {..} else {no access}` (or <=, >, >= with tid on
+    // the matching side) with e free of tid: only tids below e (or e + 1)
+    // can access memory.  Returns the expression and whether to add 1.
+    int thread_limit(int si, bool &plus1) const {
+        const SNode &s = ir.s[si];
+        if (s.kind != B_IF || has_access(s.kids[1])) return -1;
+        const XNode &c = ir.x[s.e];
+        const XNode *A = c.a >= 0 ? &ir.x[c.a] : nullptr, *B = c.b >= 0 ? &ir.x[c.b] : nullptr;
+        if (!A || !B) return -1;
+        if ((c.op == B_LT || c.op == B_LE) && A->op == B_TID && !mentions_tid(ir, c.b)) {
+            plus1 = c.op == B_LE;
+            return c.b;
+        }
+        if ((c.op == B_GT || c.op == B_GE) && B->op == B_TID && !mentions_tid(ir, c.a)) {
+            plus1 = c.op == B_GE;
+            return c.a;
+        }
+        return -1;
+    }
+
     void run() {
         std::vector<uint32_t> map(ir.nslots + 1, 0);
         renumber(ir.root, map, 0);
@@ -859,6 +886,22 @@ struct Planner {
                 nest_depth = 0;
                 gen_s(ne.leaf);
                 code->push_back(U_END);
+                // thread limit (32-bit evaluator only: no overflow to detect)
+                bool plus1 = false;
+                const int lim = plan.wide ? -1 : thread_limit(ne.leaf, plus1);
+                if (lim >= 0) {
+                    plan.leaf_guard.push_back((int)code->size());
+                    stack_max = 0;
+                    gen_block(lim);
+                    if (plus1) {
+                        // the block's postfix code grows by one immediate op
+                        (*code)[plan.leaf_guard.back()] += 2;
+                        code->push_back(X_ADDC);
+                        code->push_back(1);
+                    }
+                } else {
+                    plan.leaf_guard.push_back(-1);
+                }
                 int id = (int)plan.leaf_code.size() - 1;
                 code_of_leaf[ne.leaf] = id;
                 plan.nest_leaf_code.push_back(id);

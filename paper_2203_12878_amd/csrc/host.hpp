@@ -73,6 +73,7 @@ struct Plan {
     std::vector<int> leaf_ids;
     std::vector<std::vector<uint32_t>> leaf_code;
     std::vector<int> nest_leaf_code;   // per nest: index into leaf_code
+    std::vector<int> leaf_guard;       // per leaf code: offset of its thread-limit block, or -1
 };
 
 int compile_text(const char *text, size_t len, std::vector<uint32_t> &out);

@@ -288,6 +288,16 @@ DEV void load_fixed(const NestDesc &nd, const FixedVal *__restrict__ fixed, T *v
     }
 }
 
+// Tids that can access memory in the current iteration: [0, limit).
+template <typename T>
+DEV uint32_t tid_limit(const NestDesc &nd, const uint32_t *__restrict__ code, const T *vars, uint32_t n) {
+    if (nd.guard_off == NONE32) return n;
+    bool o = false;
+    const uint32_t *g = code + nd.guard_off;
+    const T e = eval_expr<T, false>(g + 1, rfl(g[0]), vars, (T)0, o);
+    return (uint64_t)e < (uint64_t)n ? (uint32_t)e : n;
+}
+
 // Phase of iteration f (digits decoded from scratch).
 DEV uint64_t phase_of(const NestDesc &nd, uint64_t f) {
     uint64_t ph = nd.phase_base, rem = f;
@@ -346,7 +356,7 @@ __global__ __launch_bounds__(WG) void k_count(const Item *__restrict__ items, co
             cur = odo.phase;
         }
         // leaf loops never write for^S slots (binders are distinct)
-        run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+        if (it.tid0 < tid_limit<T>(nd, code, vars, pd.n)) run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
         odo.next(nd, vars);
     }
     if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
@@ -418,7 +428,7 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
     for (uint64_t f = it.f0; f < it.f1; f++) {
         const uint32_t i = (uint32_t)(odo.phase - it.k_lo);
         const unsigned long long b = lds_base[i];
-        if (b != ~0ull) {
+        if (b != ~0ull && it.tid0 < tid_limit<T>(nd, code, vars, pd.n)) {
             sink.cur = &lds_cur[i];
             sink.base = b;
             run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
@@ -514,7 +524,8 @@ DEV uint32_t rec_tid(unsigned long long r) { return (uint32_t)(r >> 1) & 0x7FFFF
 // Run state of the segmented conflict scan (all wave-uniform).
 struct RunState {
     bool open;
-    uint32_t idx, t0, t1, wf;
+    unsigned long long key;
+    uint32_t t0, t1, wf;
     bool t0w, in_t0;
 };
 
@@ -544,9 +555,9 @@ DEV void run_segment(RunState &st, uint32_t s, uint32_t e, uint64_t G, uint64_t 
     }
 }
 
-DEV bool run_close(const RunState &st, uint32_t &ridx, uint32_t &ri1, uint32_t &ri2) {
+DEV bool run_close(const RunState &st, unsigned long long &rkey, uint32_t &ri1, uint32_t &ri2) {
     if (st.t1 != NONE32 && (st.t0w || st.wf != NONE32)) {
-        ridx = st.idx;
+        rkey = st.key;
         ri1 = st.t0;
         ri2 = st.t0w ? st.t1 : st.wf;
         return true;
@@ -554,90 +565,119 @@ DEV bool run_close(const RunState &st, uint32_t &ridx, uint32_t &ri1, uint32_t &
     return false;
 }
 
+DEV uint32_t ctz64(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
+
 // First racy run (in sorted order) whose head lies in [a, b) of the sorted
-// array a_[0..cnt); runs starting before a belong to the previous wave and
-// the last run may extend past b.  Heads come from a ballot of key changes.
-DEV bool wave_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t a, uint32_t b, uint32_t &ridx,
-                         uint32_t &ri1, uint32_t &ri2) {
+// array rec[0..cnt); runs starting before a belong to the previous wave and
+// the last run may extend past b.  The array is read 64 records at a time:
+// group heads (index changes), tid changes and writers are three ballots.
+// Every head lane resolves its own group when the group ends inside the
+// chunk (lane-parallel mask arithmetic plus one cross-lane read); only a
+// group that crosses into the next chunk is carried in wave-uniform state.
+DEV bool wave_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t a, uint32_t b, uint32_t tb,
+                         unsigned long long &rkey, uint32_t &ri1, uint32_t &ri2) {
     RunState st{false, 0, 0, NONE32, NONE32, false, false};
     const uint32_t lane = lane_id();
+    const uint32_t gsh = tb + 1;
+    const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
     for (uint32_t base = a; base < cnt; base += 64) {
         if (!st.open && base >= b) break;
         const uint32_t i = base + lane;
         const bool valid = i < cnt;
         const unsigned long long r = valid ? rec[i] : ~0ull;
         const unsigned long long rp = (valid && i > 0) ? rec[i - 1] : ~0ull;
-        const uint32_t idx = rec_idx(r), tidv = rec_tid(r);
-        const bool head = valid && (i == 0 || rec_idx(rp) != idx);
-        const bool gch = valid && !head && rec_tid(rp) != tidv;
+        const unsigned long long grp = r >> gsh;
+        const uint32_t tidv = (uint32_t)(r >> 1) & tmask;
+        const bool head = valid && (i == 0 || (rp >> gsh) != grp);
+        const bool gch = valid && !head && ((uint32_t)(rp >> 1) & tmask) != tidv;
+        const uint32_t glo = (uint32_t)grp, ghi = (uint32_t)(grp >> 32);
         const uint64_t H = ballot(head), G = ballot(gch), Wm = ballot(valid && (r & 1ull));
-        const uint64_t V = ballot(valid);
-        const uint32_t nvalid = (uint32_t)__builtin_popcountll(V);   // valid lanes are a prefix
+        const uint32_t nvalid = (uint32_t)__builtin_popcountll(ballot(valid));   // valid lanes are a prefix
+        const bool at_end = base + nvalid >= cnt;
         uint32_t pos = 0;
         if (st.open) {
-            const uint64_t hn = H;
-            const uint32_t end = hn ? (uint32_t)__builtin_ctzll(hn) : nvalid;
+            // the group carried in from the previous chunk
+            const uint32_t end = H ? ctz64(H) : nvalid;
             run_segment(st, 0, end, G, Wm, tidv);
-            if (end < 64 && (end < nvalid || base + end >= cnt)) {
+            if (end < nvalid || at_end) {
                 st.open = false;
-                if (run_close(st, ridx, ri1, ri2)) return true;
+                if (run_close(st, rkey, ri1, ri2)) return true;
             } else {
-                continue;   // run spans the whole chunk
+                continue;   // the group spans the whole chunk
             }
             pos = end;
         }
         const uint32_t lim = (b > base) ? (b - base < 64 ? b - base : 64) : 0;
-        uint64_t hs = H & bits_range(pos, lim);
-        while (hs) {
-            const uint32_t h = (uint32_t)__builtin_ctzll(hs);
-            const uint64_t nxt = H & bits_from(h + 1);
-            const uint32_t end = nxt ? (uint32_t)__builtin_ctzll(nxt) : nvalid;
-            hs &= bits_from(h + 1);
-            if (end == h + 1 && (end < nvalid || base + end >= cnt)) continue;   // single record: no race
+        const uint64_t mine_m = H & bits_range(pos, lim);
+        // per head lane: its group [lane, e)
+        const uint64_t after = H & bits_from(lane + 1);
+        const uint32_t e = after ? ctz64(after) : nvalid;
+        const bool closed = e < nvalid || at_end;
+        const bool mine = ((mine_m >> lane) & 1ull) != 0;
+        bool racy = false;
+        uint32_t src = lane;
+        if (mine && closed) {
+            const uint64_t g = G & bits_range(lane, e);
+            const uint32_t gb = g ? ctz64(g) : e;
+            const bool t0w = (Wm & bits_range(lane, gb)) != 0;
+            const uint64_t wl = Wm & bits_range(gb, e);
+            racy = gb < e && (t0w || wl != 0);
+            if (racy) src = t0w ? gb : ctz64(wl);
+        }
+        const uint32_t partner = __shfl(tidv, (int)src);
+        const uint64_t R = ballot(racy);
+        if (R) {
+            const uint32_t f = ctz64(R);
+            rkey = ((unsigned long long)readlane(ghi, f) << 32) | readlane(glo, f);
+            ri1 = readlane(tidv, f);
+            ri2 = readlane(partner, f);
+            return true;
+        }
+        // a group of this wave that continues in the next chunk
+        const uint64_t open_m = mine_m & ~ballot(closed);
+        if (open_m) {
+            const uint32_t h = ctz64(open_m);
             st.open = true;
-            st.idx = readlane(idx, h);
+            st.key = ((unsigned long long)readlane(ghi, h) << 32) | readlane(glo, h);
             st.t0 = readlane(tidv, h);
             st.t1 = NONE32;
             st.wf = NONE32;
             st.in_t0 = true;
             st.t0w = false;
-            run_segment(st, h, end, G, Wm, tidv);
-            if (end < nvalid || base + end >= cnt) {
-                st.open = false;
-                if (run_close(st, ridx, ri1, ri2)) return true;
-            } else {
-                break;   // continues in the next chunk
-            }
+            run_segment(st, h, nvalid, G, Wm, tidv);
         }
     }
-    if (st.open && run_close(st, ridx, ri1, ri2)) return true;
+    if (st.open && run_close(st, rkey, ri1, ri2)) return true;
     return false;
 }
 
-// Workgroup-wide: first racy run of the sorted LDS array.  Returns found
-// (uniform across the block) and the run in *out (idx, i1, i2).
-DEV bool block_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t *lds_res /* 4 waves x 4 */,
-                          uint32_t &idx, uint32_t &i1, uint32_t &i2) {
+// Workgroup-wide: first racy group of the sorted LDS array (records with
+// tid bits tb).  Returns found (uniform across the block) and the group
+// key (record >> (tb + 1)) with its pair.
+DEV bool block_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t tb,
+                          uint32_t *lds_res /* 4 waves x 5 */, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t nw = blockDim.x >> 6;
     const uint32_t per = (cnt + nw - 1) / nw;
     const uint32_t a = wave * per, b = (a + per < cnt) ? a + per : cnt;
-    uint32_t ri = 0, r1 = 0, r2 = 0;
-    bool f = (a < cnt) ? wave_first_racy(rec, cnt, a, b, ri, r1, r2) : false;
+    unsigned long long rk = 0;
+    uint32_t r1 = 0, r2 = 0;
+    bool f = (a < cnt) ? wave_first_racy(rec, cnt, a, b, tb, rk, r1, r2) : false;
     if (lane_id() == 0) {
-        lds_res[wave * 4 + 0] = f ? 1u : 0u;
-        lds_res[wave * 4 + 1] = ri;
-        lds_res[wave * 4 + 2] = r1;
-        lds_res[wave * 4 + 3] = r2;
+        lds_res[wave * 5 + 0] = f ? 1u : 0u;
+        lds_res[wave * 5 + 1] = (uint32_t)rk;
+        lds_res[wave * 5 + 2] = (uint32_t)(rk >> 32);
+        lds_res[wave * 5 + 3] = r1;
+        lds_res[wave * 5 + 4] = r2;
     }
     __syncthreads();
     bool found = false;
     for (uint32_t w = 0; w < nw; w++) {
-        if (lds_res[w * 4]) {
+        if (lds_res[w * 5]) {
             found = true;
-            idx = lds_res[w * 4 + 1];
-            i1 = lds_res[w * 4 + 2];
-            i2 = lds_res[w * 4 + 3];
+            key = ((unsigned long long)lds_res[w * 5 + 2] << 32) | lds_res[w * 5 + 1];
+            i1 = lds_res[w * 5 + 3];
+            i2 = lds_res[w * 5 + 4];
             break;
         }
     }
@@ -660,6 +700,8 @@ DEV void offer(Best *best, Cand *cand, uint32_t proto, uint32_t phase, uint32_t 
 struct FusedSink {
     unsigned long long *lds;
     uint32_t *lds_n;
+    unsigned long long pre;     // phase-in-group prefix of the key
+    uint32_t ish;               // index shift (tid bits + 1)
     uint32_t tid;
     DEV void acc(bool act, uint32_t idx, uint32_t mode) {
         const uint64_t m = ballot(act);
@@ -669,7 +711,7 @@ struct FusedSink {
         off = __shfl(off, 0);
         const uint32_t pos = off + mbcnt(m);
         if (act && pos < (uint32_t)TILE)
-            lds[pos] = ((unsigned long long)idx << 32) | ((unsigned long long)tid << 1) | mode;
+            lds[pos] = pre | ((unsigned long long)idx << ish) | ((unsigned long long)tid << 1) | mode;
     }
 };
 
@@ -683,7 +725,7 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
                                                Cand *__restrict__ cands, Best *__restrict__ best, uint32_t tile) {
     __shared__ unsigned long long lds_rec[TILE];
     __shared__ uint32_t lds_n;
-    __shared__ uint32_t lds_res[16];
+    __shared__ uint32_t lds_res[20];
     __shared__ uint32_t lds_unit;
     __shared__ uint32_t lds_ovf;
     // persistent: workgroups pull units (largest first) from a device queue
@@ -703,36 +745,64 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
         bool have = false;
         unsigned long long total = 0;
         bool ovf = false;
-        for (uint64_t k = u.k0; k < u.k1; k++) {
-            if (!stat) {
-                const unsigned long long cnt_k = phase_counts[k];
-                if (cnt_k == 0 || cnt_k > (unsigned long long)tile) continue;   // empty or handled in HBM
-            }
+        const bool pack = pd.pack != 0;
+        const uint32_t tb = pack ? pd.tb : 31u;
+        const uint32_t ish = tb + 1;
+        const uint32_t psh = pack ? pd.ib + tb + 1 : 64u;   // phase-in-group shift
+        uint64_t k = u.k0;
+        while (k < u.k1) {
+            // one group of consecutive phases whose events fit one tile
+            const uint64_t gk0 = k;
             if (threadIdx.x == 0) lds_n = 0;
             __syncthreads();
-            for (uint32_t ni = 0; ni < pd.nnests; ni++) {
-                const NestDesc &nd = nests[pd.nest0 + ni];
-                if (k < nd.phase_base || k > nd.phase_last) continue;
-                const uint64_t fa = first_iter_at(nd, k);
-                if (fa >= nd.iters) continue;
-                T vars[MAXSLOTS];
-                for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
-                load_fixed<T>(nd, fixed, vars);
-                Odo<T> odo;
-                odo.start(nd, fa, vars);
-                const uint32_t *leaf = code + nd.code_off;
-                for (uint64_t f = fa; f < nd.iters && odo.phase == k; f++) {
-                    for (uint32_t t0 = 0; t0 < pd.n; t0 += WG) {
-                        const uint32_t tid = t0 + threadIdx.x;
-                        FusedSink sink{lds_rec, &lds_n, tid};
-                        run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
-                    }
-                    odo.next(nd, vars);
+            uint32_t est = 0, before = 0;
+            bool any = false;
+            while (k < u.k1) {
+                uint32_t c;
+                if (!stat) {
+                    const unsigned long long ck = phase_counts[k];
+                    if (ck == 0 || ck > (unsigned long long)tile) { k++; continue; }   // empty or in HBM
+                    c = (uint32_t)ck;
+                } else {
+                    c = pd.phase_bound;
                 }
+                if (any && (!pack || est + c > (uint32_t)TILE)) break;
+                const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
+                for (uint32_t ni = 0; ni < pd.nnests; ni++) {
+                    const NestDesc &nd = nests[pd.nest0 + ni];
+                    if (k < nd.phase_base || k > nd.phase_last) continue;
+                    const uint64_t fa = first_iter_at(nd, k);
+                    if (fa >= nd.iters) continue;
+                    T vars[MAXSLOTS];
+                    for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+                    load_fixed<T>(nd, fixed, vars);
+                    Odo<T> odo;
+                    odo.start(nd, fa, vars);
+                    const uint32_t *leaf = code + nd.code_off;
+                    for (uint64_t f = fa; f < nd.iters && odo.phase == k; f++) {
+                        const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
+                        for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
+                            const uint32_t tid = t0 + threadIdx.x;
+                            FusedSink sink{lds_rec, &lds_n, pre, ish, tid};
+                            run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
+                        }
+                        odo.next(nd, vars);
+                    }
+                }
+                if (stat) {
+                    __syncthreads();
+                    const uint32_t now = lds_n;
+                    if (threadIdx.x == 0) phase_counts[k] = now - before;
+                    before = now;
+                    __syncthreads();
+                }
+                est += c;
+                any = true;
+                k++;
             }
+            if (!any) break;
             __syncthreads();
             uint32_t cnt = lds_n;
-            if (stat && threadIdx.x == 0) phase_counts[k] = cnt;
             total += cnt;
             if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: bounded by count or plan
             if (cnt == 0) {
@@ -744,11 +814,14 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
             for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[i] = ~0ull;
             __syncthreads();
             block_sort(lds_rec, npow);
-            uint32_t ridx, r1, r2;
-            const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
+            unsigned long long key;
+            uint32_t r1, r2;
+            const bool f = block_first_racy(lds_rec, cnt, tb, lds_res, key, r1, r2);
             if (f && !have) {
                 have = true;
-                if (threadIdx.x == 0) offer(best, my, u.proto, (uint32_t)(k - pd.phase_off), ridx, r1, r2);
+                const uint64_t kk = gk0 + (pack ? (key >> pd.ib) : 0ull);
+                const uint32_t idx = pack ? (uint32_t)(key & ((1ull << pd.ib) - 1)) : (uint32_t)key;
+                if (threadIdx.x == 0) offer(best, my, u.proto, (uint32_t)(kk - pd.phase_off), idx, r1, r2);
             }
             __syncthreads();
         }
@@ -825,7 +898,7 @@ __global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const uns
 __global__ __launch_bounds__(WG) void k_tile(const Tile *__restrict__ tiles, const unsigned long long *__restrict__ recs,
                                               Cand *__restrict__ cands, Best *__restrict__ best) {
     __shared__ unsigned long long lds_rec[TILE];
-    __shared__ uint32_t lds_res[16];
+    __shared__ uint32_t lds_res[20];
     const Tile t = tiles[blockIdx.x];
     Cand *my = &cands[blockIdx.x];
     if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = t.proto; }
@@ -835,9 +908,10 @@ __global__ __launch_bounds__(WG) void k_tile(const Tile *__restrict__ tiles, con
     for (uint32_t i = threadIdx.x; i < npow; i += WG) lds_rec[i] = i < cnt ? recs[t.start + i] : ~0ull;
     __syncthreads();
     block_sort(lds_rec, npow);
-    uint32_t ridx, r1, r2;
-    const bool f = block_first_racy(lds_rec, cnt, lds_res, ridx, r1, r2);
-    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, ridx, r1, r2);
+    uint32_t r1, r2;
+    unsigned long long rkey;
+    const bool f = block_first_racy(lds_rec, cnt, 31, lds_res, rkey, r1, r2);
+    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)rkey, r1, r2);
 }
 
 // ============================================= single-index large groups

@@ -57,7 +57,7 @@ class Stats:
     completed: int = 0
     records: int = 0
     batches: int = 0
-    max_batch_bytes: int = 0
+    max_batch_bytes: int = 0          # largest footprint of a batch of two or more requests
     max_batch_size: int = 0
     latencies: List[float] = field(default_factory=list)
 
@@ -157,7 +157,8 @@ class Server:
                 st = self.stats
                 st.batches += 1
                 st.max_batch_size = max(st.max_batch_size, len(batch))
-                st.max_batch_bytes = max(st.max_batch_bytes, sum(r.bytes for r in batch))
+                if len(batch) > 1:
+                    st.max_batch_bytes = max(st.max_batch_bytes, sum(r.bytes for r in batch))
                 for r, x in zip(batch, res):
                     r.t_done = now
                     st.completed += 1

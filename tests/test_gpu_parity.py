@@ -89,6 +89,26 @@ def test_big_phase_path(chk):
     _same(chk.check_batch(items), o2.check_many(items, jobs=8), items)
 
 
+def test_thread_limit_guards(chk):
+    # leaves `if tid < e {..} else {no access}` run only the tids below e
+    items = [("(if (<= tid 3) (wr (mod tid 2)) (skip))", 9),
+             ("(fors l 0 5 (seq (if (> (>> 16 l) tid) (wr (+ tid 1)) (skip)) (sync)))", 20),
+             ("(fors l 0 5 (if (> (>> 16 l) tid) (wr (+ tid 1)) (skip)))", 20),
+             ("(if (< tid 0) (wr 0) (skip))", 300),
+             ("(if (< tid 100000) (wr (mod tid 1000)) (foru x 0 3 (skip)))", 4000),
+             ("(fors x 0 3 (if (>= (* x 300) tid) (rd (mod tid 7)) (skip)))", 1000),
+             ("(fors x 0 40 (seq (if (< tid (* x 700)) (wr (+ (* x 100000) tid)) (skip)) (rd (+ (* x 100000) 5))))", 30000)]
+    _same(chk.check_batch(items), o2.check_many(items, jobs=8), items)
+
+
+def test_packed_fused_groups(chk):
+    # many small phases per fused group (packed keys), racy in a late phase
+    items = [("(fors x 0 500 (seq (wr (+ (* tid 4) (mod x 4))) (sync) (rd (+ (* (mod (+ tid 1) 50) 4) (mod x 4))) (sync)))", 50),
+             ("(fors x 0 300 (seq (wr (+ (* tid 4) (mod x 4))) (rd (+ (* (mod (+ tid 1) 50) 4) (mod (+ x 1) 4))) (sync)))", 50),
+             ("(fors x 0 300 (seq (wr (+ (* tid 4) (mod x 4))) (if (= x 277) (rd (+ (* (mod (+ tid 1) 50) 4) (mod x 4))) (skip)) (sync)))", 50)]
+    _same(chk.check_batch(items), o2.check_many(items, jobs=8), items)
+
+
 def test_tree_batch_closed_form(chk):
     import test_oracle as T
     batch = w.gen_tree_batch(0, count=64, kmax=16)

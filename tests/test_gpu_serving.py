@@ -20,7 +20,7 @@ def test_serving_mix_equals_alone():
         st = srv.stats
     assert st.completed == len(reqs)
     assert st.batches < len(reqs)          # requests were batched
-    assert st.max_batch_bytes <= budget or st.max_batch_size == 1
+    assert st.max_batch_bytes <= budget   # a request above the budget runs alone
     chk = drf.Checker(0)
     alone = [chk.check(t, n) for _, t, n, _ in reqs]
     chk.close()
