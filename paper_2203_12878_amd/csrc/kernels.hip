@@ -438,6 +438,12 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
 }
 
 // ======================================================= LDS sort + scan
+// LDS record arrays are padded by one slot per 32 keys: thread blocks of
+// E consecutive keys then start in different banks (no 64-way conflicts
+// when a thread loads or stores its block).
+constexpr uint32_t TILE_LDS = TILE + TILE / 32;
+DEV uint32_t ph(uint32_t i) { return i + (i >> 5); }
+
 // Bitonic sort of n = 256 * E u64 keys in LDS by a 256-thread workgroup.
 // Thread t keeps a[E*t .. E*t+E) in registers for every stride below E;
 // larger strides exchange through LDS, with all loads of a stage issued
@@ -450,12 +456,12 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
     const uint32_t half = n >> 1;
     unsigned long long v[E];
 #pragma unroll
-    for (int j = 0; j < E; j++) v[j] = a[g0 + j];
+    for (int j = 0; j < E; j++) v[j] = a[ph(g0 + j)];
     for (uint32_t size = 2; size <= n; size <<= 1) {
         if ((size >> 1) >= (uint32_t)E) {
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < E; j++) a[g0 + j] = v[j];
+            for (int j = 0; j < E; j++) a[ph(g0 + j)] = v[j];
             __syncthreads();
             for (uint32_t stride = size >> 1; stride >= (uint32_t)E; stride >>= 1) {
                 unsigned long long x[PAIRS], y[PAIRS];
@@ -465,8 +471,8 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
                     const uint32_t i = t + (uint32_t)j * 256u;
                     lo[j] = 2 * i - (i & (stride - 1));
                     if (i < half) {
-                        x[j] = a[lo[j]];
-                        y[j] = a[lo[j] + stride];
+                        x[j] = a[ph(lo[j])];
+                        y[j] = a[ph(lo[j] + stride)];
                     }
                 }
 #pragma unroll
@@ -475,14 +481,14 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
                     if (i < half) {
                         const bool asc = (lo[j] & size) == 0;
                         const bool sw = (x[j] > y[j]) == asc;
-                        a[lo[j]] = sw ? y[j] : x[j];
-                        a[lo[j] + stride] = sw ? x[j] : y[j];
+                        a[ph(lo[j])] = sw ? y[j] : x[j];
+                        a[ph(lo[j] + stride)] = sw ? x[j] : y[j];
                     }
                 }
                 __syncthreads();
             }
 #pragma unroll
-            for (int j = 0; j < E; j++) v[j] = a[g0 + j];
+            for (int j = 0; j < E; j++) v[j] = a[ph(g0 + j)];
         }
 #pragma unroll
         for (int st = E / 2; st >= 1; st >>= 1) {
@@ -502,7 +508,7 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < E; j++) a[g0 + j] = v[j];
+    for (int j = 0; j < E; j++) a[ph(g0 + j)] = v[j];
     __syncthreads();
 }
 
@@ -584,8 +590,8 @@ DEV bool wave_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t a
         if (!st.open && base >= b) break;
         const uint32_t i = base + lane;
         const bool valid = i < cnt;
-        const unsigned long long r = valid ? rec[i] : ~0ull;
-        const unsigned long long rp = (valid && i > 0) ? rec[i - 1] : ~0ull;
+        const unsigned long long r = valid ? rec[ph(i)] : ~0ull;
+        const unsigned long long rp = (valid && i > 0) ? rec[ph(i - 1)] : ~0ull;
         const unsigned long long grp = r >> gsh;
         const uint32_t tidv = (uint32_t)(r >> 1) & tmask;
         const bool head = valid && (i == 0 || (rp >> gsh) != grp);
@@ -711,7 +717,7 @@ struct FusedSink {
         off = __shfl(off, 0);
         const uint32_t pos = off + mbcnt(m);
         if (act && pos < (uint32_t)TILE)
-            lds[pos] = pre | ((unsigned long long)idx << ish) | ((unsigned long long)tid << 1) | mode;
+            lds[ph(pos)] = pre | ((unsigned long long)idx << ish) | ((unsigned long long)tid << 1) | mode;
     }
 };
 
@@ -723,7 +729,7 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
                                                unsigned long long *__restrict__ phase_counts,
                                                unsigned long long *__restrict__ nrec, uint32_t *__restrict__ ovf_flags,
                                                Cand *__restrict__ cands, Best *__restrict__ best, uint32_t tile) {
-    __shared__ unsigned long long lds_rec[TILE];
+    __shared__ unsigned long long lds_rec[TILE_LDS];
     __shared__ uint32_t lds_n;
     __shared__ uint32_t lds_res[20];
     __shared__ uint32_t lds_unit;
@@ -811,7 +817,7 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
             }
             uint32_t npow = 256;
             while (npow < cnt) npow <<= 1;
-            for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[i] = ~0ull;
+            for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[ph(i)] = ~0ull;
             __syncthreads();
             block_sort(lds_rec, npow);
             unsigned long long key;
@@ -895,18 +901,47 @@ __global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const uns
 }
 
 // ================================================================== tiles
+// Loads src[0..cnt) into a[0..256*E) (padding ~0).  Every load of a thread
+// is issued before its first LDS store, so the E HBM round trips overlap
+// instead of queueing; lanes past the end re-read the last record (no
+// branch around the loads, which would force a wait after each).
+template <int E>
+DEV void tile_load_e(unsigned long long *a, const unsigned long long *__restrict__ src, uint32_t cnt) {
+    unsigned long long u[E];
+    const uint32_t last = cnt - 1;
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+        const uint32_t i = (uint32_t)j * WG + threadIdx.x;
+        u[j] = src[i < cnt ? i : last];
+    }
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+        const uint32_t i = (uint32_t)j * WG + threadIdx.x;
+        a[ph(i)] = i < cnt ? u[j] : ~0ull;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(WG) void k_tile(const Tile *__restrict__ tiles, const unsigned long long *__restrict__ recs,
                                               Cand *__restrict__ cands, Best *__restrict__ best) {
-    __shared__ unsigned long long lds_rec[TILE];
+    __shared__ unsigned long long lds_rec[TILE_LDS];
     __shared__ uint32_t lds_res[20];
     const Tile t = tiles[blockIdx.x];
     Cand *my = &cands[blockIdx.x];
     if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = t.proto; }
     const uint32_t cnt = t.len;
+    if (cnt == 0) return;
     uint32_t npow = 256;
     while (npow < cnt) npow <<= 1;
-    for (uint32_t i = threadIdx.x; i < npow; i += WG) lds_rec[i] = i < cnt ? recs[t.start + i] : ~0ull;
-    __syncthreads();
+    const unsigned long long *src = recs + t.start;
+    switch (npow >> 8) {
+    case 1: tile_load_e<1>(lds_rec, src, cnt); break;
+    case 2: tile_load_e<2>(lds_rec, src, cnt); break;
+    case 4: tile_load_e<4>(lds_rec, src, cnt); break;
+    case 8: tile_load_e<8>(lds_rec, src, cnt); break;
+    case 16: tile_load_e<16>(lds_rec, src, cnt); break;
+    default: tile_load_e<32>(lds_rec, src, cnt); break;
+    }
     block_sort(lds_rec, npow);
     uint32_t r1, r2;
     unsigned long long rkey;
