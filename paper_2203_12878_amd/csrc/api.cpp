@@ -596,20 +596,26 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             const Seg &sg = segs[s2];
             const uint32_t nd = 1u << sg.dbits;
             // consecutive small buckets of one segment are contiguous and
-            // hold disjoint index values: one tile takes several of them
+            // hold disjoint index values: one tile takes several of them.
+            // When one bucket spans few enough index values for the tile
+            // kernel's singleton filter, a tile stays within that span.
             Tile cur{0, 0, sg.proto, sg.phase, 0};
+            uint32_t cur_d0 = 0;
+            const bool span_cap = sg.shift < FILTER_BITS;
             for (uint32_t d = 0; d < nd; d++) {
                 const uint64_t a0 = starts[s2 * sstride + d];
                 const uint64_t e = (d + 1 < nd) ? starts[s2 * sstride + d + 1] : out_start[s2] + sg.len;
                 const uint64_t len = e - a0;
                 if (len == 0) continue;
                 if (len <= (uint64_t)tile) {
-                    if (cur.len && cur.start + cur.len == a0 && cur.len + len <= (uint64_t)tile) {
+                    const bool in_span = !span_cap || ((uint64_t)(d - cur_d0 + 1) << sg.shift) <= (1ull << FILTER_BITS);
+                    if (cur.len && cur.start + cur.len == a0 && cur.len + len <= (uint64_t)tile && in_span) {
                         cur.len += (uint32_t)len;
                     } else {
                         if (cur.len) tiles.push_back(cur);
                         cur.start = a0;
                         cur.len = (uint32_t)len;
+                        cur_d0 = d;
                     }
                     continue;
                 }

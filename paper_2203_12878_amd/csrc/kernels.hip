@@ -444,11 +444,11 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
 constexpr uint32_t TILE_LDS = TILE + TILE / 32;
 DEV uint32_t ph(uint32_t i) { return i + (i >> 5); }
 
-// Bitonic sort of n = 256 * E u64 keys in LDS by a 256-thread workgroup.
+// Bitonic sort of n = NT * E u64 keys in LDS by an NT-thread workgroup.
 // Thread t keeps a[E*t .. E*t+E) in registers for every stride below E;
 // larger strides exchange through LDS, with all loads of a stage issued
 // before any store (pairs of one stage are disjoint).
-template <int E>
+template <int E, int NT = WG>
 DEV void block_sort_e(unsigned long long *a, uint32_t n) {
     constexpr int PAIRS = (E / 2 > 0) ? E / 2 : 1;
     const uint32_t t = threadIdx.x;
@@ -468,7 +468,7 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
                 uint32_t lo[PAIRS];
 #pragma unroll
                 for (int j = 0; j < PAIRS; j++) {
-                    const uint32_t i = t + (uint32_t)j * 256u;
+                    const uint32_t i = t + (uint32_t)j * (uint32_t)NT;
                     lo[j] = 2 * i - (i & (stride - 1));
                     if (i < half) {
                         x[j] = a[ph(lo[j])];
@@ -477,7 +477,7 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
                 }
 #pragma unroll
                 for (int j = 0; j < PAIRS; j++) {
-                    const uint32_t i = t + (uint32_t)j * 256u;
+                    const uint32_t i = t + (uint32_t)j * (uint32_t)NT;
                     if (i < half) {
                         const bool asc = (lo[j] & size) == 0;
                         const bool sw = (x[j] > y[j]) == asc;
@@ -661,7 +661,7 @@ DEV bool wave_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t a
 // tid bits tb).  Returns found (uniform across the block) and the group
 // key (record >> (tb + 1)) with its pair.
 DEV bool block_first_racy(const unsigned long long *rec, uint32_t cnt, uint32_t tb,
-                          uint32_t *lds_res /* 4 waves x 5 */, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+                          uint32_t *lds_res /* 5 words per wave */, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t nw = blockDim.x >> 6;
     const uint32_t per = (cnt + nw - 1) / nw;
@@ -901,57 +901,6 @@ __global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const uns
 }
 
 // ================================================================== tiles
-// Loads src[0..cnt) into a[0..256*E) (padding ~0).  Every load of a thread
-// is issued before its first LDS store, so the E HBM round trips overlap
-// instead of queueing; lanes past the end re-read the last record (no
-// branch around the loads, which would force a wait after each).
-template <int E>
-DEV void tile_load_e(unsigned long long *a, const unsigned long long *__restrict__ src, uint32_t cnt) {
-    unsigned long long u[E];
-    const uint32_t last = cnt - 1;
-#pragma unroll
-    for (int j = 0; j < E; j++) {
-        const uint32_t i = (uint32_t)j * WG + threadIdx.x;
-        u[j] = src[i < cnt ? i : last];
-    }
-#pragma unroll
-    for (int j = 0; j < E; j++) {
-        const uint32_t i = (uint32_t)j * WG + threadIdx.x;
-        a[ph(i)] = i < cnt ? u[j] : ~0ull;
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(WG) void k_tile(const Tile *__restrict__ tiles, const unsigned long long *__restrict__ recs,
-                                              Cand *__restrict__ cands, Best *__restrict__ best) {
-    __shared__ unsigned long long lds_rec[TILE_LDS];
-    __shared__ uint32_t lds_res[20];
-    const Tile t = tiles[blockIdx.x];
-    Cand *my = &cands[blockIdx.x];
-    if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = t.proto; }
-    const uint32_t cnt = t.len;
-    if (cnt == 0) return;
-    uint32_t npow = 256;
-    while (npow < cnt) npow <<= 1;
-    const unsigned long long *src = recs + t.start;
-    switch (npow >> 8) {
-    case 1: tile_load_e<1>(lds_rec, src, cnt); break;
-    case 2: tile_load_e<2>(lds_rec, src, cnt); break;
-    case 4: tile_load_e<4>(lds_rec, src, cnt); break;
-    case 8: tile_load_e<8>(lds_rec, src, cnt); break;
-    case 16: tile_load_e<16>(lds_rec, src, cnt); break;
-    default: tile_load_e<32>(lds_rec, src, cnt); break;
-    }
-    block_sort(lds_rec, npow);
-    uint32_t r1, r2;
-    unsigned long long rkey;
-    const bool f = block_first_racy(lds_rec, cnt, 31, lds_res, rkey, r1, r2);
-    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)rkey, r1, r2);
-}
-
-// ============================================= single-index large groups
-// All records of a group share one index.  Pass 1: least tid, least writer,
-// largest tid.  Pass 2 (when the least tid writes): least tid != t0.
 DEV uint32_t wave_min(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w < v ? w : v; }
     return v;
@@ -960,6 +909,215 @@ DEV uint32_t wave_max(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w > v ? w : v; }
     return v;
 }
+// Workgroup min / max through red[0 .. waves) (barriers on entry and exit).
+DEV uint32_t block_min(uint32_t v, uint32_t *red) {
+    v = wave_min(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = red[0];
+    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) r = red[w] < r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+DEV uint32_t block_max(uint32_t v, uint32_t *red) {
+    v = wave_max(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = red[0];
+    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) r = red[w] > r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+// A tile is decided by one of three methods, chosen from the index span of
+// its records (all of one phase):
+//  table   span <= TBL_CELLS: per index cell, the least tid, the least
+//          writing tid and the least tid other than the first, by LDS
+//          atomics.  Definition 1 needs nothing else: the cell races iff a
+//          second tid and a writer exist, and the witness is (least tid,
+//          least other tid if the least tid writes, else least writer).
+//  filter  span <= 2^FILTER_BITS: a seen / repeated bitmap pair removes
+//          every index touched by a single record (one access cannot race);
+//          the records left are sorted and scanned.
+//  sort    otherwise, or when more than FILTER_CAP records survive the
+//          filter: the whole tile is sorted and scanned.
+// Tiles run 512-thread workgroups: at most 16 records per thread stay in
+// registers, and the two workgroups the LDS admits per CU give 4 waves per
+// SIMD.
+constexpr int TWG = 512;
+constexpr uint32_t TBL_CELLS = (TILE_LDS * 2) / 3;       // three u32 per cell
+constexpr uint32_t FILTER_WORDS = 1u << (FILTER_BITS - 5);
+constexpr uint32_t FILTER_CAP = 3968;                    // ph() slots below the repeated bitmap
+static_assert(2 * FILTER_WORDS <= 2 * TILE_LDS, "filter bitmaps exceed the tile LDS");
+static_assert(FILTER_CAP - 1 + (FILTER_CAP - 1) / 32 < FILTER_WORDS / 2, "filter output overlaps its bitmap");
+static_assert(TILE % TWG == 0 && TILE / TWG <= 16, "tile records per thread");
+constexpr uint32_t RED_CAND = 5 * (TWG / 64);            // candidate counter, after the scan's slots
+constexpr uint32_t RED_WORDS = RED_CAND + 1;
+
+// Sorts a[0..n) (n a power of two, TWG <= n <= TILE) with a TWG-thread
+// workgroup and returns the first racy group of its cnt records.
+DEV bool tile_sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t *red, unsigned long long &key,
+                        uint32_t &i1, uint32_t &i2) {
+    switch (n / TWG) {
+    case 1: block_sort_e<1, TWG>(a, n); break;
+    case 2: block_sort_e<2, TWG>(a, n); break;
+    case 4: block_sort_e<4, TWG>(a, n); break;
+    case 8: block_sort_e<8, TWG>(a, n); break;
+    default: block_sort_e<16, TWG>(a, n); break;
+    }
+    return block_first_racy(a, cnt, 31, red, key, i1, i2);
+}
+
+// Records are read straight into registers (element i = j * TWG + tid, all
+// loads issued before any use; lanes past the end re-read the last record,
+// so no branch sits between the loads).
+template <int E>
+DEV void tile_run(const Tile &t, const unsigned long long *__restrict__ src, unsigned long long *a, uint32_t *red,
+                  Cand *my, Best *best) {
+    const uint32_t cnt = t.len;
+    uint32_t *w32 = reinterpret_cast<uint32_t *>(a);
+    unsigned long long u[E];
+    const uint32_t last = cnt - 1;
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+        const uint32_t i = (uint32_t)j * TWG + threadIdx.x;
+        u[j] = src[i < cnt ? i : last];
+    }
+    uint32_t lo = NONE32, hi = 0;
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+        const uint32_t x = rec_idx(u[j]);
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    lo = block_min(lo, red);
+    hi = block_max(hi, red);
+    const uint64_t span = (uint64_t)hi - lo + 1;
+
+    if (span <= TBL_CELLS) {
+        const uint32_t sp = (uint32_t)span;
+        uint32_t *t0 = w32, *w0 = w32 + sp, *t1 = w32 + 2 * sp;
+        for (uint32_t k = threadIdx.x; k < 3 * sp; k += TWG) w32[k] = NONE32;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((uint32_t)j * TWG + threadIdx.x < cnt) {
+                const uint32_t b = rec_idx(u[j]) - lo, tid = rec_tid(u[j]);
+                atomicMin(&t0[b], tid);
+                if (u[j] & 1ull) atomicMin(&w0[b], tid);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((uint32_t)j * TWG + threadIdx.x < cnt) {
+                const uint32_t b = rec_idx(u[j]) - lo, tid = rec_tid(u[j]);
+                if (tid != t0[b]) atomicMin(&t1[b], tid);
+            }
+        }
+        __syncthreads();
+        uint32_t first = NONE32;
+        for (uint32_t k = threadIdx.x; k < sp; k += TWG) {
+            if (t1[k] != NONE32 && w0[k] != NONE32) { first = k; break; }
+        }
+        first = block_min(first, red);
+        if (first != NONE32 && threadIdx.x == 0) {
+            const uint32_t a0 = t0[first], aw = w0[first];
+            offer(best, my, t.proto, t.phase, lo + first, a0, aw == a0 ? t1[first] : aw);
+        }
+        return;
+    }
+
+    if (span <= (1ull << FILTER_BITS)) {
+        const uint32_t nw = (uint32_t)((span + 31) >> 5);
+        uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
+        for (uint32_t k = threadIdx.x; k < nw; k += TWG) {
+            seen[k] = 0;
+            rep[k] = 0;
+        }
+        if (threadIdx.x == 0) red[RED_CAND] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((uint32_t)j * TWG + threadIdx.x < cnt) {
+                const uint32_t b = rec_idx(u[j]) - lo, bit = 1u << (b & 31);
+                if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
+            }
+        }
+        __syncthreads();
+        // survivors go to a[ph(0..)], which lies below the repeated bitmap
+        // (the seen bitmap is no longer read)
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            const uint32_t b = rec_idx(u[j]) - lo;
+            const bool keep = (uint32_t)j * TWG + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
+            const uint64_t m = ballot(keep);
+            if (m) {
+                uint32_t base = 0;
+                if (lane_id() == 0) base = atomicAdd(&red[RED_CAND], (uint32_t)__builtin_popcountll(m));
+                base = __shfl(base, 0);
+                const uint32_t pos = base + mbcnt(m);
+                if (keep && pos < FILTER_CAP) a[ph(pos)] = u[j];
+            }
+        }
+        __syncthreads();
+        const uint32_t nc = red[RED_CAND];
+        if (nc <= FILTER_CAP) {
+            if (nc == 0) return;
+            uint32_t np = TWG;
+            while (np < nc) np <<= 1;
+            for (uint32_t k = nc + threadIdx.x; k < np; k += TWG) a[ph(k)] = ~0ull;
+            __syncthreads();
+            uint32_t r1, r2;
+            unsigned long long rkey;
+            const bool f = tile_sort_scan(a, np, nc, red, rkey, r1, r2);
+            if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)rkey, r1, r2);
+            return;
+        }
+        // every thread has read nc and no bitmap is read again: the whole
+        // tile is sorted below
+    }
+
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+        const uint32_t i = (uint32_t)j * TWG + threadIdx.x;
+        a[ph(i)] = i < cnt ? u[j] : ~0ull;
+    }
+    __syncthreads();
+    uint32_t r1, r2;
+    unsigned long long rkey;
+    const bool f = tile_sort_scan(a, (uint32_t)TWG * E, cnt, red, rkey, r1, r2);
+    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)rkey, r1, r2);
+}
+
+// two workgroups per CU fit the LDS: ask for the registers of four waves per SIMD
+__global__ __launch_bounds__(TWG) __attribute__((amdgpu_waves_per_eu(4))) void k_tile(
+    const Tile *__restrict__ tiles, const unsigned long long *__restrict__ recs, Cand *__restrict__ cands,
+    Best *__restrict__ best) {
+    __shared__ unsigned long long lds_rec[TILE_LDS];
+    __shared__ uint32_t lds_res[RED_WORDS];
+    const Tile t = tiles[blockIdx.x];
+    Cand *my = &cands[blockIdx.x];
+    if (threadIdx.x == 0) { my->key = ~0ull; my->pair = 0; my->proto = t.proto; }
+    const uint32_t cnt = t.len;
+    if (cnt == 0) return;
+    uint32_t npow = TWG;
+    while (npow < cnt) npow <<= 1;
+    const unsigned long long *src = recs + t.start;
+    switch (npow / TWG) {
+    case 1: tile_run<1>(t, src, lds_rec, lds_res, my, best); break;
+    case 2: tile_run<2>(t, src, lds_rec, lds_res, my, best); break;
+    case 4: tile_run<4>(t, src, lds_rec, lds_res, my, best); break;
+    case 8: tile_run<8>(t, src, lds_rec, lds_res, my, best); break;
+    default: tile_run<16>(t, src, lds_rec, lds_res, my, best); break;
+    }
+}
+
+// ============================================= single-index large groups
+// All records of a group share one index.  Pass 1: least tid, least writer,
+// largest tid.  Pass 2 (when the least tid writes): least tid != t0.
 
 __global__ __launch_bounds__(WG) void k_single1(const Group *__restrict__ groups, uint32_t ngroups,
                                                  const unsigned long long *__restrict__ recs, SingleAcc *__restrict__ acc) {
@@ -1182,7 +1340,7 @@ hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long lo
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands, Best *best,
                         hipStream_t s) {
-    return launch(k_tile, dim3(ntiles), dim3(WG), s, tiles, recs, cands, best);
+    return launch(k_tile, dim3(ntiles), dim3(TWG), s, tiles, recs, cands, best);
 }
 
 hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned long long *recs, SingleAcc *acc,
