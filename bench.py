@@ -104,6 +104,10 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "small", "mixed", "tree"])
     ap.add_argument("--path", default="auto", choices=["auto", "plain", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-events", type=int, default=0, help="tuning override (0: library default)")
+    ap.add_argument("--digit-bits", type=int, default=0)
+    ap.add_argument("--unit-events", type=int, default=0)
+    ap.add_argument("--item-events", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build checks protocols on one GPU; --gpus %d is not supported "
@@ -116,6 +120,8 @@ def main():
     items, desc = workload(args.workload)
     path = args.path if args.path != "auto" else ("plain" if len(items) == 1 else "batch")
     chk = drf.Checker(0)
+    chk.set_tuning(tile_events=args.tile_events, digit_bits=args.digit_bits, unit_events=args.unit_events,
+                   item_events=args.item_events)
     lib = drf.lib()
     lib.drf_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
     batch = drf.Batch(items, 0)
@@ -180,7 +186,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "path": path, "protocols": len(items),
-                   "records_per_step": records, "racy_protocols": racy},
+                   "records_per_step": records, "racy_protocols": racy, "tuning": chk.tuning()},
         "parity_vs_stored_oracle": parity,
         "roofline": roof,
         "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,

@@ -22,9 +22,11 @@
 // whole device work (fills are kernels, never memset nodes).
 #include <hip/hip_runtime.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <functional>
 #include <thread>
 #include <vector>
@@ -49,7 +51,7 @@ struct drf_ctx {
     hipEvent_t counted = nullptr;
     bool done_valid = false;
     uint32_t cus = 256;
-    drf_tuning tune = {(uint32_t)drf::TILE, 8, 1u << 12, 1u << 16};
+    drf_tuning tune = {(uint32_t)drf::TILE, 8, 1u << 16, 1u << 16};
     // per-kernel-class timing
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -59,6 +61,23 @@ struct drf_ctx {
 };
 
 namespace {
+
+// Host stage timings on stderr when the environment sets DRF_TRACE (a
+// development aid; off by default).
+struct Trace {
+    using clock = std::chrono::steady_clock;
+    bool on;
+    clock::time_point t0, last;
+    Trace() : on(getenv("DRF_TRACE") != nullptr) { t0 = last = clock::now(); }
+    void mark(const char *what, unsigned long long a = 0) {
+        if (!on) return;
+        const clock::time_point n = clock::now();
+        fprintf(stderr, "[drf] %-22s +%9.3f ms  (%9.3f)  %llu\n", what,
+                std::chrono::duration<double, std::milli>(n - last).count(),
+                std::chrono::duration<double, std::milli>(n - t0).count(), a);
+        last = n;
+    }
+};
 
 
 constexpr uint64_t CAND_CAP = 1ull << 20;      // candidates per launch
@@ -215,6 +234,7 @@ struct Call {
     hipStream_t st;
     uint32_t count;
     Recorder *rec = nullptr;
+    Trace tr;
 
     // run a device operation on the call's stream (and record it)
     template <class F>
@@ -319,6 +339,8 @@ struct Call {
                 {
                     const int g = p.leaf_guard[p.nest_leaf_code[j]];
                     nd.guard_off = g < 0 ? NONE32 : leaf_off[p.nest_leaf_code[j]] + (uint32_t)g;
+                    const int cl = p.leaf_cal[p.nest_leaf_code[j]];
+                    nd.cal_off = cl < 0 ? NONE32 : leaf_off[p.nest_leaf_code[j]] + (uint32_t)cl;
                 }
                 nd.iters = ne.iters;
                 nd.phase_base = pd.phase_off + ne.phase_base;
@@ -490,6 +512,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         }
     }
 
+    C.tr.mark("wave emit launched", recs);
     auto run_groups = [&](const std::vector<Group> &groups, const unsigned long long *recbuf) {
         for (uint64_t g0 = 0; g0 < groups.size(); g0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(groups.size() - g0, CAND_CAP);
@@ -588,6 +611,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         std::vector<uint64_t> starts(segs.size() * sstride);
         hipck(hipMemcpyAsync(starts.data(), dstarts, starts.size() * 8, hipMemcpyDeviceToHost, st));
         C.sync();
+        C.tr.mark("level partitioned", segs.size());
 
         std::vector<Seg> next;
         std::vector<Tile> tiles;
@@ -640,6 +664,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         segs.swap(next);
         std::swap(in, out);
         C.sync();
+        C.tr.mark("level tiles done", tiles.size());
     }
 }
 
@@ -657,7 +682,9 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         hipck(hipSetDevice(ctx->device));
         if (ctx->done_valid) hipck(hipStreamWaitEvent(st, ctx->done, 0));
         C.plan_all(code, code_off, nthreads);
+        C.tr.mark("plan", count);
         C.build_blob();
+        C.tr.mark("blob", C.items[0].size() + C.items[1].size());
         if (C.total_phases > phase_cap || (C.total_phases && !d_phase_counts)) return DRF_E_ARG;
         // upper bound on fused units: one per small phase at most
         C.layout_a(C.total_phases + 1);
@@ -742,6 +769,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 });
             }
         }
+        C.tr.mark("count launched");
         std::vector<uint64_t> counts(C.total_phases);
         std::vector<uint32_t> hovf(count);
         if (dynamic) {
@@ -764,12 +792,14 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             fused(C.sunits[w], w == 1, C.o_sunits[w], work, 0);
         }
 
+        C.tr.mark("static fused launched");
         // ---- classification of the counted protocols
         std::vector<uint64_t> nrec(count, 0);
         std::vector<Unit> units[2];
         std::vector<BigPhase> big;
         if (dynamic) {
             hipck(hipEventSynchronize(ctx->counted));
+            C.tr.mark("counts on host");
             for (uint32_t i = 0; i < count; i++) {
                 if (C.status[i] || C.stat[i]) continue;
                 if (hovf[i]) { C.status[i] = DRF_E_RANGE; continue; }
@@ -809,6 +839,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 }
                 fused(units[w], w == 1, C.o_units, work, ev);
             }
+            C.tr.mark("fused launched", units[0].size() + units[1].size());
         }
 
         // ---- big phases, in waves under the scratch budget
@@ -848,7 +879,9 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                                                     W.witems[1].size(), tile, ctx->tune.digit_bits).bytes);
             }
             grow(ctx->poolB, ctx->sizeB, needB);
+            C.tr.mark("waves planned", waves.size());
             for (const Wave &W : waves) run_wave(C, big, W, best, cand);
+            C.tr.mark("waves done");
         }
 
         // ---- results
@@ -871,6 +904,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         // pageable uploads are staged synchronously; the last ones must
         // still be complete before the host copies go away
         hipck(hipStreamSynchronize(st));
+        C.tr.mark("done");
         prof_collect(ctx);
         return DRF_OK;
     } catch (Fail f) {

@@ -50,6 +50,22 @@ enum : uint32_t {
     X_AFF,         // nterms c_lo c_hi {var c} * nterms  (var: slot, or NONE32 for tid)
 };
 
+// Compiled access leaf: a leaf that is a straight-line sequence of
+// accesses (possibly inside a thread-limit guard) whose index expressions
+// are a chain of operations applied to tid, each with a tid-free operand.
+// The tid-free operands ("uniform slots") are evaluated once per iteration;
+// each lane then runs its short chain.  Layout (words, from cal_off):
+//   nacc nuni
+//   nuni x { len <postfix X_* code over loop variables> }
+//   nacc x { mode nops { opw arg } * nops }
+// opw = C_* | (C_UNI if arg is a uniform slot, else arg is the immediate).
+enum : uint32_t {
+    C_ADD = 1, C_MUL, C_MONUS, C_RMONUS, C_DIV, C_MOD, C_SHL, C_SHR, C_MIN, C_MAX, C_AND,
+    C_UNI = 0x100,
+};
+constexpr uint32_t CAL_MAXU = 32;    // uniform slots of one leaf (a chunk then stages >= 64 iterations)
+constexpr uint32_t CAL_MAXOPS = 16;  // chain operations of one access
+
 struct ProtoDesc {
     uint32_t n;          // threads
     uint32_t wide;       // 64-bit evaluator with overflow checks
@@ -75,7 +91,7 @@ struct NestDesc {
     uint32_t rec_bound;    // per-lane access events per iteration (upper bound, saturated)
     uint32_t guard_off;    // thread-limit expression (word offset) or NONE32: only tids below
                            // its value can access memory in an iteration
-    uint32_t pad2;
+    uint32_t cal_off;      // compiled access leaf (word offset) or NONE32
     uint64_t iters;        // product of trips (>= 1)
     uint64_t phase_base;   // global phase id of iteration 0
     uint64_t phase_last;   // global phase id of the last iteration

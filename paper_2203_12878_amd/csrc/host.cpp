@@ -813,6 +813,121 @@ struct Planner {
         }
     }
 
+    // ---- compiled access leaf (see drf_layout.hpp)
+    struct COp {
+        uint32_t op;
+        uint64_t imm;              // constant part of the operand
+        std::vector<int> adds;     // tid-free expression nodes added to it
+    };
+
+    // e as a chain of operations on tid with tid-free operands
+    bool chain(int e, std::vector<COp> &ops) {
+        const XNode &x = ir.x[e];
+        if (x.op == B_TID) return true;
+        if (x.a < 0 || x.b < 0) return false;
+        const bool ta = mentions_tid(ir, x.a), tbv = mentions_tid(ir, x.b);
+        if (ta == tbv) return false;
+        const int v = ta ? x.a : x.b, u = ta ? x.b : x.a;
+        uint32_t op = 0;
+        switch (x.op) {
+        case B_ADD: op = C_ADD; break;
+        case B_MUL: op = C_MUL; break;
+        case B_MIN: op = C_MIN; break;
+        case B_MAX: op = C_MAX; break;
+        case B_MONUS: op = ta ? C_MONUS : C_RMONUS; break;
+        case B_DIV: op = ta ? C_DIV : 0; break;
+        case B_MOD: op = ta ? C_MOD : 0; break;
+        case B_SHL: op = ta ? C_SHL : 0; break;
+        case B_SHR: op = ta ? C_SHR : 0; break;
+        default: break;
+        }
+        if (!op || !chain(v, ops)) return false;
+        COp c{op, 0, {}};
+        const XNode &U = ir.x[u];
+        if (is_const(U)) c.imm = U.val; else c.adds.push_back(u);
+        // consecutive additions share one operand: with every value of the
+        // original expression below 2^32 the regrouped sum is too
+        if (op == C_ADD && !ops.empty() && ops.back().op == C_ADD) {
+            ops.back().imm += c.imm;
+            ops.back().adds.insert(ops.back().adds.end(), c.adds.begin(), c.adds.end());
+            return true;
+        }
+        ops.push_back(std::move(c));
+        return true;
+    }
+
+    bool straight(int si, std::vector<int> &accs) const {
+        const SNode &s = ir.s[si];
+        if (s.kind == B_SKIP) return true;
+        if (s.kind == B_ACC) { accs.push_back(si); return true; }
+        if (s.kind != B_SEQ) return false;
+        for (int k : s.kids) if (!straight(k, accs)) return false;
+        return true;
+    }
+
+    // Appends the compiled access leaf of `leaf` to the current code and
+    // returns its offset, or -1 when the leaf has another shape.  `guarded`:
+    // the leaf is a thread-limit if whose accesses are all in its then part.
+    int gen_cal(int leaf, bool guarded) {
+        if (plan.wide) return -1;
+        std::vector<int> accs;
+        if (!straight(guarded ? ir.s[leaf].kids[0] : leaf, accs) || accs.empty()) return -1;
+        std::vector<std::vector<COp>> chains(accs.size());
+        for (size_t j = 0; j < accs.size(); j++) {
+            if (!chain(ir.s[accs[j]].e, chains[j]) || chains[j].size() > CAL_MAXOPS) return -1;
+            for (auto &c : chains[j]) if (c.imm >= (1ull << 32)) return -1;
+        }
+        // uniform slots (identical operands share one)
+        std::vector<std::pair<std::vector<int>, uint64_t>> slots;
+        auto slot_of = [&](const COp &c) -> int {
+            for (size_t i = 0; i < slots.size(); i++)
+                if (slots[i].first == c.adds && slots[i].second == c.imm) return (int)i;
+            slots.push_back({c.adds, c.imm});
+            return (int)slots.size() - 1;
+        };
+        std::vector<std::vector<std::pair<uint32_t, uint32_t>>> enc(accs.size());
+        for (size_t j = 0; j < accs.size(); j++) {
+            for (auto &c : chains[j]) {
+                if (!c.adds.empty()) {
+                    enc[j].push_back({c.op | C_UNI, (uint32_t)slot_of(c)});
+                    continue;
+                }
+                const uint64_t k = c.imm;
+                const bool pow2 = k && !(k & (k - 1));
+                if (c.op == C_MOD && pow2) enc[j].push_back({C_AND, (uint32_t)(k - 1)});
+                else if (c.op == C_DIV && pow2) enc[j].push_back({C_SHR, (uint32_t)__builtin_ctzll(k)});
+                else enc[j].push_back({c.op, (uint32_t)k});
+            }
+        }
+        if (slots.size() > CAL_MAXU) return -1;
+        auto &c = *code;
+        const int at = (int)c.size();
+        c.push_back((uint32_t)accs.size());
+        c.push_back((uint32_t)slots.size());
+        for (auto &sl : slots) {
+            const size_t len_at = c.size();
+            c.push_back(0);
+            stack_depth = 0;
+            stack_max = 0;
+            for (size_t i = 0; i < sl.first.size(); i++) {
+                gen_x(sl.first[i]);
+                if (i) { c.push_back(X_ADD); push_depth(-1); }
+            }
+            if (sl.second) { c.push_back(X_ADDC); c.push_back((uint32_t)sl.second); }
+            c[len_at] = (uint32_t)(c.size() - len_at - 1);
+            if (stack_max > MAXSTACK) {
+                c.resize((size_t)at);
+                return -1;
+            }
+        }
+        for (size_t j = 0; j < accs.size(); j++) {
+            c.push_back(ir.s[accs[j]].mode);
+            c.push_back((uint32_t)enc[j].size());
+            for (auto &o : enc[j]) { c.push_back(o.first); c.push_back(o.second); }
+        }
+        return at;
+    }
+
     bool has_access(int si) const {
         const SNode &s = ir.s[si];
         if (s.kind == B_ACC) return true;
@@ -902,6 +1017,7 @@ struct Planner {
                 } else {
                     plan.leaf_guard.push_back(-1);
                 }
+                plan.leaf_cal.push_back(gen_cal(ne.leaf, lim >= 0));
                 int id = (int)plan.leaf_code.size() - 1;
                 code_of_leaf[ne.leaf] = id;
                 plan.nest_leaf_code.push_back(id);

@@ -74,6 +74,7 @@ struct Plan {
     std::vector<std::vector<uint32_t>> leaf_code;
     std::vector<int> nest_leaf_code;   // per nest: index into leaf_code
     std::vector<int> leaf_guard;       // per leaf code: offset of its thread-limit block, or -1
+    std::vector<int> leaf_cal;         // per leaf code: offset of its compiled access leaf, or -1
 };
 
 int compile_text(const char *text, size_t len, std::vector<uint32_t> &out);

@@ -245,14 +245,22 @@ struct Odo {
     DEV void start(const NestDesc &nd, uint64_t f, T *vars) {
         nloops = nd.nloops;
         phase = nd.phase_base;
+        const bool narrow = nd.iters <= 0xFFFFFFFFull;   // every trip and f fit 32 bits
         uint64_t rem = f;
 #pragma unroll
         for (int l = MAXLOOPS - 1; l >= 0; l--) {
             digit[l] = 0;
             if (l < (int)nloops) {
                 const uint64_t t = nd.trip[l];
-                const uint64_t d = rem % t;
-                rem /= t;
+                uint64_t d;
+                if (narrow) {
+                    const uint32_t r32 = (uint32_t)rem, t32 = (uint32_t)t;
+                    d = r32 % t32;
+                    rem = r32 / t32;
+                } else {
+                    d = rem % t;
+                    rem /= t;
+                }
                 digit[l] = d;
                 vars[nd.slot[l]] = (T)(nd.lo[l] + d);
                 phase += d * nd.stride[l];
@@ -301,6 +309,15 @@ DEV uint32_t tid_limit(const NestDesc &nd, const uint32_t *__restrict__ code, co
 // Phase of iteration f (digits decoded from scratch).
 DEV uint64_t phase_of(const NestDesc &nd, uint64_t f) {
     uint64_t ph = nd.phase_base, rem = f;
+    if (nd.iters <= 0xFFFFFFFFull) {
+        uint32_t r32 = (uint32_t)rem;
+        for (int l = (int)nd.nloops - 1; l >= 0; l--) {
+            const uint32_t t32 = (uint32_t)nd.trip[l];
+            ph += (uint64_t)(r32 % t32) * nd.stride[l];
+            r32 /= t32;
+        }
+        return ph;
+    }
     for (int l = (int)nd.nloops - 1; l >= 0; l--) {
         ph += (rem % nd.trip[l]) * nd.stride[l];
         rem /= nd.trip[l];
@@ -319,6 +336,25 @@ DEV uint64_t first_iter_at(const NestDesc &nd, uint64_t k) {
 }
 
 // ============================================================= count pass
+// Compiled leaf: every lane below the thread limit performs every access
+// once per iteration, so one lane per iteration finds the counts.
+template <typename T>
+DEV void count_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const FixedVal *__restrict__ fixed,
+                   const uint32_t *__restrict__ code, uint32_t *lds_cnt) {
+    const uint32_t nacc = rfl(code[nd.cal_off]);
+    const uint64_t nit = it.f1 - it.f0;
+    for (uint64_t q = threadIdx.x; q < nit; q += WG) {
+        T vars[MAXSLOTS];
+        for (int z = 0; z < MAXSLOTS; z++) vars[z] = 0;
+        load_fixed<T>(nd, fixed, vars);
+        Odo<T> odo;
+        odo.start(nd, it.f0 + q, vars);
+        const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
+        const uint32_t na = lim > it.tid0 ? (lim - it.tid0 < (uint32_t)WG ? lim - it.tid0 : (uint32_t)WG) : 0u;
+        if (na) atomicAdd(&lds_cnt[odo.phase - it.k_lo], nacc * na);
+    }
+}
+
 struct CountSink {
     uint32_t n;   // wave-uniform running count of the current phase
     DEV void acc(bool act, uint32_t, uint32_t) { n += __builtin_popcountll(ballot(act)); }
@@ -338,29 +374,35 @@ __global__ __launch_bounds__(WG) void k_count(const Item *__restrict__ items, co
     for (uint32_t i = threadIdx.x; i < span; i += WG) lds_cnt[i] = 0;
     __syncthreads();
 
-    T vars[MAXSLOTS];
-    for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
-    load_fixed<T>(nd, fixed, vars);
-    Odo<T> odo;
-    odo.start(nd, it.f0, vars);
-    const uint32_t tid = it.tid0 + threadIdx.x;
-    const bool act0 = tid < pd.n;
-    const uint32_t *leaf = code + nd.code_off;
-    bool ovf = false;
-    CountSink sink{0};
-    uint64_t cur = odo.phase;
-    for (uint64_t f = it.f0; f < it.f1; f++) {
-        if (odo.phase != cur) {
-            if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
-            sink.n = 0;
-            cur = odo.phase;
+    bool compiled = false;
+    if constexpr (!WIDE) compiled = nd.cal_off != NONE32;
+    if (compiled) {
+        count_cal<T>(it, nd, pd, fixed, code, lds_cnt);
+    } else {
+        T vars[MAXSLOTS];
+        for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+        load_fixed<T>(nd, fixed, vars);
+        Odo<T> odo;
+        odo.start(nd, it.f0, vars);
+        const uint32_t tid = it.tid0 + threadIdx.x;
+        const bool act0 = tid < pd.n;
+        const uint32_t *leaf = code + nd.code_off;
+        bool ovf = false;
+        CountSink sink{0};
+        uint64_t cur = odo.phase;
+        for (uint64_t f = it.f0; f < it.f1; f++) {
+            if (odo.phase != cur) {
+                if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
+                sink.n = 0;
+                cur = odo.phase;
+            }
+            // leaf loops never write for^S slots (binders are distinct)
+            if (it.tid0 < tid_limit<T>(nd, code, vars, pd.n)) run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+            odo.next(nd, vars);
         }
-        // leaf loops never write for^S slots (binders are distinct)
-        if (it.tid0 < tid_limit<T>(nd, code, vars, pd.n)) run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
-        odo.next(nd, vars);
+        if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
+        if (ballot(ovf) != 0 && lane_id() == 0) atomicOr(&proto_ovf[nd.proto], 1u);
     }
-    if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
-    if (ballot(ovf) != 0 && lane_id() == 0) atomicOr(&proto_ovf[nd.proto], 1u);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < span; i += WG) {
         const uint32_t c = lds_cnt[i];
@@ -387,6 +429,102 @@ struct EmitSink {
     }
 };
 
+// Compiled leaf: per chunk of iterations the workgroup first evaluates the
+// uniform slots (slot-major, iterations padded to whole waves so every wave
+// runs one slot program), the phase and the thread limit of each iteration
+// into LDS; then each lane runs its access chains.
+constexpr uint32_t CAL_U = 2048;    // staged uniform values per chunk
+constexpr uint32_t CAL_CH = 256;    // iterations per chunk
+
+struct CalLds {
+    uint32_t u[CAL_U];
+    uint32_t ph[CAL_CH];
+    uint32_t lim[CAL_CH];
+    uint32_t uoff[CAL_MAXU + 1];
+};
+
+template <typename T>
+DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const FixedVal *__restrict__ fixed,
+                  const uint32_t *__restrict__ code, const unsigned long long *lds_base, uint32_t *lds_cur,
+                  unsigned long long *__restrict__ recs, unsigned long long cap, CalLds &L) {
+    const uint32_t *cal = code + nd.cal_off;
+    const uint32_t nacc = rfl(cal[0]), nuni = rfl(cal[1]);
+    if (threadIdx.x == 0) {
+        uint32_t o = 2;
+        for (uint32_t z = 0; z < nuni; z++) {
+            L.uoff[z] = o;
+            o += 1 + cal[o];
+        }
+        L.uoff[CAL_MAXU] = o;
+    }
+    __syncthreads();
+    const uint32_t *acc0 = cal + rfl(L.uoff[CAL_MAXU]);
+    const uint32_t nu = nuni ? nuni : 1u;
+    static_assert(CAL_U / CAL_MAXU >= 64, "a chunk must hold one wave of iterations");
+    const uint32_t chmax = (CAL_U / nu) / 64 * 64 < CAL_CH ? (CAL_U / nu) / 64 * 64 : CAL_CH;   // >= 64
+    const uint32_t tid = it.tid0 + threadIdx.x;
+    const bool act0 = tid < pd.n;
+    EmitSink sink{nullptr, 0, recs, 0, tid};
+    sink.cap = cap;
+    for (uint64_t fc = it.f0; fc < it.f1; fc += chmax) {
+        const uint32_t ch = (uint32_t)(it.f1 - fc < chmax ? it.f1 - fc : chmax);
+        const uint32_t chp = (ch + 63) & ~63u;
+        for (uint32_t q = threadIdx.x; q < chp * nu; q += WG) {
+            const uint32_t z = rfl(q / chp), fi = q - z * chp;   // slot is uniform per wave
+            if (fi >= ch) continue;
+            T vars[MAXSLOTS];
+            for (int y = 0; y < MAXSLOTS; y++) vars[y] = 0;
+            load_fixed<T>(nd, fixed, vars);
+            Odo<T> odo;
+            odo.start(nd, fc + fi, vars);
+            if (z == 0) {
+                L.ph[fi] = (uint32_t)(odo.phase - it.k_lo);
+                L.lim[fi] = tid_limit<T>(nd, code, vars, pd.n);
+            }
+            if (z < nuni) {
+                bool o = false;
+                const uint32_t *up = cal + rfl(L.uoff[z]);
+                L.u[q] = (uint32_t)eval_expr<T, false>(up + 1, rfl(up[0]), vars, (T)0, o);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = 0; i < ch; i++) {
+            const uint32_t pi = rfl(L.ph[i]);
+            const unsigned long long b = lds_base[pi];
+            const uint32_t lim = rfl(L.lim[i]);
+            if (b == ~0ull || it.tid0 >= lim) continue;
+            const bool act = act0 && tid < lim;
+            sink.cur = &lds_cur[pi];
+            sink.base = b;
+            const uint32_t *ap = acc0;
+            for (uint32_t j = 0; j < nacc; j++) {
+                const uint32_t mode = rfl(ap[0]), nops = rfl(ap[1]);
+                uint32_t v = tid;
+                for (uint32_t o = 0; o < nops; o++) {
+                    const uint32_t opw = rfl(ap[2 + 2 * o]), arg = rfl(ap[3 + 2 * o]);
+                    const uint32_t x = (opw & C_UNI) ? rfl(L.u[arg * chp + i]) : arg;
+                    switch (opw & 0xFFu) {
+                    case C_ADD: v += x; break;
+                    case C_MUL: v *= x; break;
+                    case C_MONUS: v = v > x ? v - x : 0u; break;
+                    case C_RMONUS: v = x > v ? x - v : 0u; break;
+                    case C_DIV: v = x ? v / x : 0u; break;
+                    case C_MOD: v = x ? v % x : v; break;
+                    case C_SHL: v = x >= 32u ? 0u : v << x; break;
+                    case C_SHR: v = x >= 32u ? 0u : v >> x; break;
+                    case C_MIN: v = v < x ? v : x; break;
+                    case C_MAX: v = v > x ? v : x; break;
+                    default: v &= x; break;   // C_AND
+                    }
+                }
+                sink.acc(act, v, mode);
+                ap += 2 + 2 * nops;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, bool WIDE>
 __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, const NestDesc *__restrict__ nests,
                                               const ProtoDesc *__restrict__ protos,
@@ -398,6 +536,7 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
                                               unsigned long long cap) {
     __shared__ unsigned long long lds_base[MAXSPAN];
     __shared__ uint32_t lds_cur[MAXSPAN];
+    __shared__ CalLds lds_cal;
     const Item it = items[blockIdx.x];
     const NestDesc &nd = nests[it.nest];
     const ProtoDesc pd = protos[nd.proto];
@@ -414,6 +553,12 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
         lds_cur[i] = 0;
     }
     __syncthreads();
+    if constexpr (!WIDE) {
+        if (nd.cal_off != NONE32) {
+            emit_cal<T>(it, nd, pd, fixed, code, lds_base, lds_cur, recs, cap, lds_cal);
+            return;
+        }
+    }
 
     T vars[MAXSLOTS];
     for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
@@ -700,6 +845,7 @@ DEV void offer(Best *best, Cand *cand, uint32_t proto, uint32_t phase, uint32_t 
 }
 
 // =============================================================== fused path
+constexpr uint32_t FN_CACHE = 16;
 // One workgroup per unit: for every phase of the unit (small phases only),
 // evaluate all access events of the phase straight into LDS, sort them and
 // scan for the first racy group.  No record touches HBM.
@@ -722,18 +868,21 @@ struct FusedSink {
 };
 
 template <typename T, bool WIDE>
-__global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, uint32_t nunits,
-                                               uint32_t *__restrict__ qhead, const NestDesc *__restrict__ nests,
-                                               const ProtoDesc *__restrict__ protos,
-                                               const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
-                                               unsigned long long *__restrict__ phase_counts,
-                                               unsigned long long *__restrict__ nrec, uint32_t *__restrict__ ovf_flags,
-                                               Cand *__restrict__ cands, Best *__restrict__ best, uint32_t tile) {
+DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
+                    const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,
+                    const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
+                    unsigned long long *__restrict__ phase_counts, unsigned long long *__restrict__ nrec,
+                    uint32_t *__restrict__ ovf_flags, Cand *__restrict__ cands, Best *__restrict__ best,
+                    uint32_t tile) {
     __shared__ unsigned long long lds_rec[TILE_LDS];
     __shared__ uint32_t lds_n;
     __shared__ uint32_t lds_res[20];
     __shared__ uint32_t lds_unit;
     __shared__ uint32_t lds_ovf;
+    // per wave: the next unprocessed iteration of each of the protocol's
+    // first FN_CACHE nests (each wave reads only its own row: no barrier)
+    __shared__ unsigned long long lds_nf[WG / 64][FN_CACHE];
+    unsigned long long *nf = lds_nf[threadIdx.x >> 6];
     // persistent: workgroups pull units (largest first) from a device queue
     for (;;) {
         if (threadIdx.x == 0) {
@@ -755,6 +904,8 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
         const uint32_t tb = pack ? pd.tb : 31u;
         const uint32_t ish = tb + 1;
         const uint32_t psh = pack ? pd.ib + tb + 1 : 64u;   // phase-in-group shift
+        const uint32_t ncache = pd.nnests < FN_CACHE ? pd.nnests : FN_CACHE;
+        for (uint32_t ni = lane_id(); ni < ncache; ni += 64) nf[ni] = first_iter_at(nests[pd.nest0 + ni], u.k0);
         uint64_t k = u.k0;
         while (k < u.k1) {
             // one group of consecutive phases whose events fit one tile
@@ -777,7 +928,10 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
                 for (uint32_t ni = 0; ni < pd.nnests; ni++) {
                     const NestDesc &nd = nests[pd.nest0 + ni];
                     if (k < nd.phase_base || k > nd.phase_last) continue;
-                    const uint64_t fa = first_iter_at(nd, k);
+                    // the cached iteration is the first of phase k unless
+                    // phases were skipped since (then search again)
+                    uint64_t fa = ni < ncache ? nf[ni] : first_iter_at(nd, k);
+                    if (fa < nd.iters && phase_of(nd, fa) < k) fa = first_iter_at(nd, k);
                     if (fa >= nd.iters) continue;
                     T vars[MAXSLOTS];
                     for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
@@ -785,7 +939,8 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
                     Odo<T> odo;
                     odo.start(nd, fa, vars);
                     const uint32_t *leaf = code + nd.code_off;
-                    for (uint64_t f = fa; f < nd.iters && odo.phase == k; f++) {
+                    uint64_t f = fa;
+                    for (; f < nd.iters && odo.phase == k; f++) {
                         const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
                         for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
                             const uint32_t tid = t0 + threadIdx.x;
@@ -794,6 +949,7 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
                         }
                         odo.next(nd, vars);
                     }
+                    if (ni < ncache) nf[ni] = f;
                 }
                 if (stat) {
                     __syncthreads();
@@ -842,6 +998,23 @@ __global__ __launch_bounds__(WG) void k_fused(const Unit *__restrict__ units, ui
         __syncthreads();
     }
 }
+
+#define FUSED_PARAMS                                                                                    \
+    const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,                       \
+        const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,                       \
+        const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,                          \
+        unsigned long long *__restrict__ phase_counts, unsigned long long *__restrict__ nrec,           \
+        uint32_t *__restrict__ ovf_flags, Cand *__restrict__ cands, Best *__restrict__ best, uint32_t tile
+#define FUSED_ARGS units, nunits, qhead, nests, protos, fixed, code, phase_counts, nrec, ovf_flags, cands, best, tile
+// 32-bit evaluator: two workgroups per CU fit the LDS, so ask for the
+// registers of two waves per SIMD.  The 64-bit one keeps its natural
+// allocation (bounding it would spill).
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_fused32(FUSED_PARAMS) {
+    fused_body<uint32_t, false>(FUSED_ARGS);
+}
+__global__ __launch_bounds__(WG) void k_fused64(FUSED_PARAMS) { fused_body<uint64_t, true>(FUSED_ARGS); }
+#undef FUSED_PARAMS
+#undef FUSED_ARGS
 
 // =============================================================== partition
 __global__ __launch_bounds__(WG) void k_hist(const Seg *__restrict__ segs, const Chunk *__restrict__ chunks,
@@ -1296,10 +1469,10 @@ hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, boo
                         Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s) {
     const uint32_t g = nunits < grid ? nunits : grid;
     if (wide)
-        return launch(k_fused<uint64_t, true>, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed,
-                      code, phase_counts, nrec, ovf_flags, cands, best, tile);
-    return launch(k_fused<uint32_t, false>, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed, code,
-                  phase_counts, nrec, ovf_flags, cands, best, tile);
+        return launch(k_fused64, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed, code, phase_counts,
+                      nrec, ovf_flags, cands, best, tile);
+    return launch(k_fused32, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed, code, phase_counts,
+                  nrec, ovf_flags, cands, best, tile);
 }
 
 hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
