@@ -229,6 +229,10 @@ struct Recorder {
     }
 };
 
+// Phases of at most this many events are decided in the fused kernel (in
+// LDS, no HBM records); larger ones go through HBM and the tile kernel.
+uint32_t small_events(const drf_ctx *ctx) { return ctx->tune.tile_events; }
+
 struct Call {
     drf_ctx *ctx;
     hipStream_t st;
@@ -265,6 +269,8 @@ struct Call {
     std::vector<uint64_t> poff;
     std::vector<ProtoDesc> protos;
     std::vector<NestDesc> nests;
+    std::vector<uint32_t> nest_tids;   // per nest: tids that may access memory
+    const Item *ditems[2] = {nullptr, nullptr};   // the items as uploaded (pool A or a recording)
     std::vector<FixedVal> fixed;
     std::vector<uint32_t> code;
     std::vector<Item> items[2];        // narrow, wide
@@ -295,7 +301,23 @@ struct Call {
         for (auto &t : th) t.join();
     }
 
+    // Events per fused unit: the tuned size, made smaller when the work is
+    // too little to give every persistent workgroup a few units.
+    uint64_t unit_size(uint64_t events) const {
+        const uint64_t slots = 4ull * 2 * ctx->cus;
+        uint64_t u = std::max<uint64_t>(events / slots, small_events(ctx));
+        return std::min<uint64_t>(u, std::max<uint64_t>(ctx->tune.unit_events, small_events(ctx)));
+    }
+
     void build_blob() {
+        uint64_t static_events = 0;
+        for (uint32_t i = 0; i < count; i++) {
+            const Plan &p = plans[i];
+            if (!p.status && p.max_phase_records <= (uint64_t)small_events(ctx))
+                static_events += (uint64_t)std::min<uint64_t>(p.num_phases * std::max<uint64_t>(1, p.max_phase_records),
+                                                              1ull << 50);
+        }
+        const uint64_t static_unit = unit_size(static_events);
         status.assign(count, 0);
         stat.assign(count, 0);
         poff.assign(count, 0);
@@ -353,14 +375,15 @@ struct Call {
                 }
                 for (auto &f : ne.fixed) fixed.push_back(FixedVal{f.first, 0, f.second});
                 nests.push_back(nd);
+                nest_tids.push_back(ne.tid_bound);
                 pd.nnests++;
             }
-            stat[i] = p.max_phase_records <= (uint64_t)ctx->tune.tile_events;
+            stat[i] = p.max_phase_records <= (uint64_t)small_events(ctx);
             if (stat[i]) {
                 if (pd.nnests == 0) continue;
                 // units of about unit_events (by the static bound), one phase at least
                 const uint64_t per = std::max<uint64_t>(1, p.max_phase_records);
-                const uint64_t step = std::max<uint64_t>(1, ctx->tune.unit_events / per);
+                const uint64_t step = std::max<uint64_t>(1, static_unit / per);
                 for (uint64_t k = 0; k < pd.nphases; k += step)
                     sunits[pd.wide].push_back(Unit{i, UNIT_STATIC, pd.phase_off + k,
                                                    pd.phase_off + std::min<uint64_t>(pd.nphases, k + step)});
@@ -372,6 +395,7 @@ struct Call {
 
     void make_items(uint32_t ni, uint32_t n, bool wide) {
         const NestDesc &nd = nests[ni];
+        n = std::min(n, nest_tids[ni]);   // blocks past the guard's bound never access memory
         if (n == 0) return;
         const uint64_t lanes = std::min<uint64_t>(n, WG);
         const uint64_t per_iter = lanes * std::max<uint64_t>(1, nd.rec_bound);
@@ -426,14 +450,17 @@ struct Call {
 struct WaveLayout {
     size_t o_bb, o_cur, o_ra, o_rb, o_hist, o_starts, o_segs, o_chunks, o_tiles, o_groups, o_acc, o_wi0, o_wi1;
     size_t bytes;
-    uint64_t hist_max, nsegs_max, chunks_max;
+    uint64_t hist_max, nsegs_max, chunks_max, tiles_cap, groups_cap;
     uint32_t sstride;
 };
 
+// A segment of any level holds more than `small` records (level 0: a big
+// phase; deeper: a bucket above the tile size, which is at least `small`).
 WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t nitems0, uint64_t nitems1,
-                       uint32_t tile, uint32_t dbits) {
+                       uint32_t tile, uint32_t small, uint32_t dbits) {
     WaveLayout L{};
-    L.nsegs_max = recs / tile + 1;
+    (void)tile;
+    L.nsegs_max = recs / ((uint64_t)small + 1) + 1;
     L.chunks_max = recs / CHUNK + L.nsegs_max + 1;
     L.hist_max = L.chunks_max << dbits;
     const uint64_t tiles_max = std::min<uint64_t>(L.nsegs_max << dbits, recs) + 1;
@@ -447,8 +474,10 @@ WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t ni
     L.o_starts = b.reserve(L.nsegs_max * L.sstride * 8);
     L.o_segs = b.reserve(L.nsegs_max * sizeof(Seg));
     L.o_chunks = b.reserve(L.chunks_max * sizeof(Chunk));
-    L.o_tiles = b.reserve(std::min<uint64_t>(tiles_max, CAND_CAP) * sizeof(Tile));
-    L.o_groups = b.reserve(std::min<uint64_t>(L.nsegs_max + nbig, CAND_CAP) * sizeof(Group));
+    L.tiles_cap = std::min<uint64_t>(tiles_max, CAND_CAP);
+    L.groups_cap = std::min<uint64_t>(L.nsegs_max + nbig, CAND_CAP);
+    L.o_tiles = b.reserve(L.tiles_cap * sizeof(Tile));
+    L.o_groups = b.reserve(L.groups_cap * sizeof(Group));
     L.o_acc = b.reserve(std::min<uint64_t>(L.nsegs_max + nbig, CAND_CAP) * sizeof(SingleAcc));
     L.o_wi0 = b.reserve(nitems0 * sizeof(Item));
     L.o_wi1 = b.reserve(nitems1 * sizeof(Item));
@@ -459,6 +488,7 @@ WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t ni
 struct Wave {
     size_t bi, be;
     uint64_t recs;
+    bool all = false;              // the wave needs every item: use the copy in pool A
     std::vector<Item> witems[2];
 };
 
@@ -476,7 +506,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     const uint64_t win_n = big[be - 1].k - win_lo + 1;
     const uint32_t tile = ctx->tune.tile_events;
     const uint32_t dbits = ctx->tune.digit_bits;
-    const WaveLayout L = wave_layout(recs, win_n, be - bi, W.witems[0].size(), W.witems[1].size(), tile, dbits);
+    const WaveLayout L =
+        wave_layout(recs, win_n, be - bi, W.witems[0].size(), W.witems[1].size(), tile, small_events(ctx), dbits);
     const uint32_t sstride = L.sstride;
 
     // ---- emit the wave's records, phase-major
@@ -491,7 +522,17 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     const unsigned long long *dbb = C.put(at<void>(B, L.o_bb), bb);
     unsigned long long *dcur = at<unsigned long long>(B, L.o_cur);
     C.fill32(dcur, 0, win_n * 8);
-    const Item *dwi[2] = {C.put(at<void>(B, L.o_wi0), W.witems[0]), C.put(at<void>(B, L.o_wi1), W.witems[1])};
+    const Item *dwi[2];
+    size_t nwi[2];
+    for (int w = 0; w < 2; w++) {
+        if (W.all) {
+            dwi[w] = C.ditems[w];
+            nwi[w] = C.items[w].size();
+        } else {
+            dwi[w] = C.put(at<void>(B, w ? L.o_wi1 : L.o_wi0), W.witems[w]);
+            nwi[w] = W.witems[w].size();
+        }
+    }
     unsigned long long *in = at<unsigned long long>(B, L.o_ra), *out = at<unsigned long long>(B, L.o_rb);
     const NestDesc *dnests = at<NestDesc>(A, C.o_nests);
     const ProtoDesc *dprotos = at<ProtoDesc>(A, C.o_protos);
@@ -500,8 +541,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     const uint32_t *ditemcnt = at<uint32_t>(A, C.o_itemcnt);
     for (int w = 0; w < 2; w++) {
         const Item *it = dwi[w];
-        for (uint64_t s0 = 0; s0 < W.witems[w].size(); s0 += 1u << 30) {
-            const uint32_t n = (uint32_t)std::min<uint64_t>(W.witems[w].size() - s0, 1u << 30);
+        for (uint64_t s0 = 0; s0 < nwi[w]; s0 += 1u << 30) {
+            const uint32_t n = (uint32_t)std::min<uint64_t>(nwi[w] - s0, 1u << 30);
             const bool wide = w == 1;
             unsigned long long *recbuf = in;
             Prof pr(ctx, st, K_EMIT, w == 0 ? recs : 0, w == 0 ? recs * 8 : 0);
@@ -517,6 +558,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         for (uint64_t g0 = 0; g0 < groups.size(); g0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(groups.size() - g0, CAND_CAP);
             std::vector<Group> part(groups.begin() + g0, groups.begin() + g0 + n);
+            if (n > L.groups_cap) throw Fail{DRF_E_NOMEM};   // beyond the reserved region
             const Group *dg = C.put(at<void>(B, L.o_groups), part);
             SingleAcc *dacc = C.rec ? (SingleAcc *)C.rec->alloc(n * sizeof(SingleAcc)) : at<SingleAcc>(B, L.o_acc);
             C.dev([=](hipStream_t s) { return launch_init_acc(dacc, (uint32_t)n, s); });
@@ -537,6 +579,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         for (uint64_t t0 = 0; t0 < tiles.size(); t0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(tiles.size() - t0, CAND_CAP);
             std::vector<Tile> part(tiles.begin() + t0, tiles.begin() + t0 + n);
+            if (n > L.tiles_cap) throw Fail{DRF_E_NOMEM};   // beyond the reserved region
             const Tile *dt = C.put(at<void>(B, L.o_tiles), part);
             uint64_t tl = 0;
             for (auto &t : part) tl += t.len;
@@ -587,6 +630,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             op += sg.len;
             for (uint32_t c = 0; c < sg.nchunks; c++) chunks.push_back(Chunk{(uint32_t)s2, c});
         }
+        // the level must fit the regions the wave layout reserved
+        if (segs.size() > L.nsegs_max || chunks.size() > L.chunks_max || hb > L.hist_max) throw Fail{DRF_E_NOMEM};
         const Seg *dsegs = C.put(at<void>(B, L.o_segs), segs);
         const Chunk *dch = C.put(at<void>(B, L.o_chunks), chunks);
         const uint32_t nch = (uint32_t)chunks.size(), nsg = (uint32_t)segs.size();
@@ -698,8 +743,9 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         const NestDesc *dnests = C.put(at<void>(A, C.o_nests), C.nests);
         const FixedVal *dfixed = C.put(at<void>(A, C.o_fixed), C.fixed);
         const uint32_t *dcode = C.put(at<void>(A, C.o_code), C.code);
-        const Item *ditems[2] = {C.put(at<void>(A, C.o_items[0]), C.items[0]),
-                                 C.put(at<void>(A, C.o_items[1]), C.items[1])};
+        C.ditems[0] = C.put(at<void>(A, C.o_items[0]), C.items[0]);
+        C.ditems[1] = C.put(at<void>(A, C.o_items[1]), C.items[1]);
+        const Item *const *ditems = C.ditems;
         // the emit pass reads the blob through pool A offsets
         if (rec) {
             // recorded calls keep the blob at its pool A offsets too (the
@@ -718,7 +764,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         C.fill32(nrec_dev, 0, count * sizeof(uint64_t));
         C.fill32(qhead, 0, 64 * sizeof(uint32_t));
         const uint32_t fgrid = ctx->cus * 2;
-        const uint32_t tile = ctx->tune.tile_events;
+        const uint32_t small = small_events(ctx);
         int qslot = 0;
 
         // fused launches (persistent, units largest first), pair pick after each
@@ -743,7 +789,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                     events = 0;
                     C.dev([=](hipStream_t s) {
                         return launch_fused(du, (uint32_t)n, qh, wide, dnests, dprotos, dfixed, dcode, phase_counts,
-                                            nrec_dev, ovf, cand, best, fgrid, tile, s);
+                                            nrec_dev, ovf, cand, best, fgrid, small, s);
                     });
                 }
                 {
@@ -799,6 +845,14 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         std::vector<BigPhase> big;
         if (dynamic) {
             hipck(hipEventSynchronize(ctx->counted));
+            uint64_t dyn_events = 0;
+            for (uint32_t i = 0; i < count; i++) {
+                if (C.status[i] || C.stat[i] || hovf[i]) continue;
+                const ProtoDesc &pd = C.protos[i];
+                for (uint64_t k = pd.phase_off; k < pd.phase_off + pd.nphases; k++)
+                    if (counts[k] <= (uint64_t)small) dyn_events += counts[k];
+            }
+            const uint64_t dyn_unit = C.unit_size(dyn_events);
             C.tr.mark("counts on host");
             for (uint32_t i = 0; i < count; i++) {
                 if (C.status[i] || C.stat[i]) continue;
@@ -809,14 +863,14 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                     const uint64_t c = counts[k];
                     nrec[i] += c;
                     if (c == 0) continue;
-                    if (c > (uint64_t)tile) {
+                    if (c > (uint64_t)small) {
                         big.push_back(BigPhase{k, c, i, (uint32_t)(k - pd.phase_off)});
                         continue;
                     }
                     if (ustart == ~0ull) ustart = k;
                     last_small = k;
                     acc += c;
-                    if (acc >= ctx->tune.unit_events) {
+                    if (acc >= dyn_unit) {
                         units[pd.wide].push_back(Unit{i, 0, ustart, k + 1});
                         ustart = ~0ull;
                         acc = 0;
@@ -834,7 +888,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 uint64_t ev = 0;
                 for (size_t j = 0; j < work.size(); j++) {
                     for (uint64_t k = units[w][j].k0; k < units[w][j].k1; k++)
-                        if (counts[k] <= (uint64_t)tile) work[j] += counts[k];
+                        if (counts[k] <= (uint64_t)small) work[j] += counts[k];
                     ev += work[j];
                 }
                 fused(units[w], w == 1, C.o_units, work, ev);
@@ -865,18 +919,27 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                     be++;
                 }
                 W.be = be;
-                const uint64_t win_lo = big[bi].k, win_n = big[be - 1].k - win_lo + 1;
-                for (int w = 0; w < 2; w++)
-                    for (const Item &it : C.items[w])
-                        if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) W.witems[w].push_back(it);
                 waves.push_back(std::move(W));
                 bi = be;
+            }
+            // one wave takes every item as uploaded; several take the items
+            // overlapping their phase window
+            if (waves.size() == 1) {
+                waves[0].all = true;
+            } else {
+                for (Wave &W : waves) {
+                    const uint64_t win_lo = big[W.bi].k, win_n = big[W.be - 1].k - win_lo + 1;
+                    for (int w = 0; w < 2; w++)
+                        for (const Item &it : C.items[w])
+                            if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) W.witems[w].push_back(it);
+                }
             }
             size_t needB = 0;
             for (const Wave &W : waves) {
                 const uint64_t win_n = big[W.be - 1].k - big[W.bi].k + 1;
                 needB = std::max(needB, wave_layout(W.recs, win_n, W.be - W.bi, W.witems[0].size(),
-                                                    W.witems[1].size(), tile, ctx->tune.digit_bits).bytes);
+                                                    W.witems[1].size(), ctx->tune.tile_events, small,
+                                                    ctx->tune.digit_bits).bytes);
             }
             grow(ctx->poolB, ctx->sizeB, needB);
             C.tr.mark("waves planned", waves.size());

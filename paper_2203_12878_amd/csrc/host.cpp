@@ -980,12 +980,23 @@ struct Planner {
             work = 0;
             u128 per = iv_stmt(ne.leaf);
             ne.rec_bound = (uint32_t)std::min<u128>(per, 0xFFFFFFFFu);
-            events = sat(events + smul(smul(per, n), it));
+            // a thread-limit guard bounds the tids that can access memory
+            ne.tid_bound = n;
+            {
+                bool plus1 = false;
+                const int lim = thread_limit(ne.leaf, plus1);
+                if (lim >= 0) {
+                    const u128 hi = sat(ivx(lim).hi + (plus1 ? 1 : 0));
+                    if (hi < (u128)n) ne.tid_bound = (uint32_t)hi;
+                }
+            }
+            const u128 tids = ne.tid_bound;
+            events = sat(events + smul(smul(per, tids), it));
             total_work = sat(total_work + smul(smul(sat(work + per + 1), n), it));
             // iterations sharing one phase: the loops whose body holds no sync
             u128 same = 1;
             for (auto &l : ne.loops) if (l.stride == 0) same = smul(same, l.trip);
-            phase_events = sat(phase_events + smul(smul(per, n), same));
+            phase_events = sat(phase_events + smul(smul(per, tids), same));
         }
         plan.max_phase_records = (uint64_t)std::min<u128>(phase_events, ~0ull);
         if (events >= MAX_EVENTS || total_work >= MAX_EVENTS * 4) { fail(DRF_E_LIMIT); return; }

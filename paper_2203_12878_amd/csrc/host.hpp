@@ -58,6 +58,7 @@ struct Nest {
     uint64_t iters = 0;
     uint64_t phase_last = 0;
     uint32_t rec_bound = 0;      // per-lane events per iteration (saturated)
+    uint32_t tid_bound = 0;      // tids below this may access memory (thread-limit guard bound, else n)
 };
 
 struct Plan {

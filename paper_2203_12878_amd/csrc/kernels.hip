@@ -844,6 +844,230 @@ DEV void offer(Best *best, Cand *cand, uint32_t proto, uint32_t phase, uint32_t 
     atomicMin(&best[proto].key, key);
 }
 
+// ======================================================= group decision
+DEV uint32_t wave_min(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w < v ? w : v; }
+    return v;
+}
+DEV uint32_t wave_max(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w > v ? w : v; }
+    return v;
+}
+
+// Workgroup min of a u32 through red[0 .. waves) (barriers on entry and exit).
+DEV uint32_t block_min(uint32_t v, uint32_t *red) {
+    v = wave_min(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = red[0];
+    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) r = red[w] < r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+// Workgroup min / max of a u64 through red[0 .. 2 * waves) (barriers on
+// entry and exit).
+DEV unsigned long long wave_min64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+DEV unsigned long long wave_max64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+template <bool MAX>
+DEV unsigned long long block_ext64(unsigned long long v, uint32_t *red) {
+    v = MAX ? wave_max64(v) : wave_min64(v);
+    __syncthreads();
+    if (lane_id() == 0) {
+        red[2 * (threadIdx.x >> 6)] = (uint32_t)v;
+        red[2 * (threadIdx.x >> 6) + 1] = (uint32_t)(v >> 32);
+    }
+    __syncthreads();
+    unsigned long long r = ((unsigned long long)red[1] << 32) | red[0];
+    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) {
+        const unsigned long long x = ((unsigned long long)red[2 * w + 1] << 32) | red[2 * w];
+        r = MAX ? (x > r ? x : r) : (x < r ? x : r);
+    }
+    __syncthreads();
+    return r;
+}
+
+// A group of records (one phase, or consecutive phases in the packed
+// layout) is decided by one of three methods, chosen from the span of its
+// cells (cell = record >> (tb + 1): the index, or phase and index):
+//  table   span <= TBL_CELLS: per cell, the least tid, the least writing
+//          tid and the least tid other than the first, by LDS atomics.
+//          Definition 1 needs nothing else: the cell races iff a second tid
+//          and a writer exist, and the witness is (least tid, least other
+//          tid if the least tid writes, else least writer).
+//  filter  span <= 2^FILTER_BITS: a seen / repeated bitmap pair removes
+//          every cell touched by a single record (one access cannot race);
+//          the records left are sorted and scanned.
+//  sort    otherwise, or when more than FILTER_CAP records survive the
+//          filter: the whole group is sorted and scanned.
+// Tiles run 512-thread workgroups: at most 16 records per thread stay in
+// registers, and the two workgroups the LDS admits per CU give 4 waves per
+// SIMD.
+constexpr int TWG = 512;
+constexpr uint32_t TBL_CELLS = (TILE_LDS * 2) / 3;       // three u32 per cell
+constexpr uint32_t FILTER_WORDS = 1u << (FILTER_BITS - 5);
+constexpr uint32_t FILTER_CAP = 3968;                    // ph() slots below the repeated bitmap
+static_assert(2 * FILTER_WORDS <= 2 * TILE_LDS, "filter bitmaps exceed the group LDS");
+static_assert(FILTER_CAP - 1 + (FILTER_CAP - 1) / 32 < FILTER_WORDS / 2, "filter output overlaps its bitmap");
+static_assert(TILE % TWG == 0 && TILE / TWG <= 16, "tile records per thread");
+static_assert(FUSED_PACK % WG == 0, "fused group size");
+constexpr uint32_t RED_WORDS = 5 * (TWG / 64) + 1;       // scan slots of the widest workgroup, then
+constexpr uint32_t RED_CAND = RED_WORDS - 1;             // the filter's candidate counter
+
+template <int E, int NT>
+DEV void sort_e(unsigned long long *a, uint32_t n) {
+    if constexpr ((uint32_t)E * NT <= (uint32_t)TILE) block_sort_e<E, NT>(a, n);
+}
+
+// Sorts a[0..n) (n a power of two, NT <= n <= TILE) with an NT-thread
+// workgroup and returns the first racy group of its cnt records.
+template <int NT>
+DEV bool sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t tb, uint32_t *red,
+                   unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+    switch (n / NT) {
+    case 1: sort_e<1, NT>(a, n); break;
+    case 2: sort_e<2, NT>(a, n); break;
+    case 4: sort_e<4, NT>(a, n); break;
+    case 8: sort_e<8, NT>(a, n); break;
+    case 16: sort_e<16, NT>(a, n); break;
+    default: sort_e<32, NT>(a, n); break;
+    }
+    return block_first_racy(a, cnt, tb, red, key, i1, i2);
+}
+
+// Decides the cnt records held in registers (element i = j * NT + thread;
+// lanes past the end hold a copy of a real record) with the LDS array a
+// (TILE_LDS words) as scratch.  Returns whether a cell races, with the
+// least racy cell and its witness pair.
+template <int E, int NT>
+DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, unsigned long long *a, uint32_t *red,
+                unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+    const uint32_t ish = tb + 1;
+    const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
+    uint32_t *w32 = reinterpret_cast<uint32_t *>(a);
+    unsigned long long lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+        const unsigned long long x = u[j] >> ish;
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    lo = block_ext64<false>(lo, red);
+    hi = block_ext64<true>(hi, red);
+    const unsigned long long span = hi - lo + 1;   // cells are below 2^63
+
+    if (span <= TBL_CELLS) {
+        const uint32_t sp = (uint32_t)span;
+        uint32_t *t0 = w32, *w0 = w32 + sp, *t1 = w32 + 2 * sp;
+        for (uint32_t k = threadIdx.x; k < 3 * sp; k += NT) w32[k] = NONE32;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((uint32_t)j * NT + threadIdx.x < cnt) {
+                const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
+                atomicMin(&t0[b], tid);
+                if (u[j] & 1ull) atomicMin(&w0[b], tid);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((uint32_t)j * NT + threadIdx.x < cnt) {
+                const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
+                if (tid != t0[b]) atomicMin(&t1[b], tid);
+            }
+        }
+        __syncthreads();
+        uint32_t first = NONE32;
+        for (uint32_t k = threadIdx.x; k < sp; k += NT) {
+            if (t1[k] != NONE32 && w0[k] != NONE32) { first = k; break; }
+        }
+        first = block_min(first, red);
+        bool found = false;
+        if (first != NONE32) {
+            found = true;
+            key = lo + first;
+            i1 = t0[first];
+            const uint32_t aw = w0[first];
+            i2 = aw == i1 ? t1[first] : aw;
+        }
+        __syncthreads();   // the table is read before the caller reuses the LDS
+        return found;
+    }
+
+    // one sort call site for both the filter's survivors and the whole group
+    uint32_t n_sort = (uint32_t)NT * E, cnt_sort = cnt;
+    bool filtered = false;
+    if (span <= (1ull << FILTER_BITS)) {
+        const uint32_t nw = (uint32_t)((span + 31) >> 5);
+        uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
+        for (uint32_t k = threadIdx.x; k < nw; k += NT) {
+            seen[k] = 0;
+            rep[k] = 0;
+        }
+        if (threadIdx.x == 0) red[RED_CAND] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((uint32_t)j * NT + threadIdx.x < cnt) {
+                const uint32_t b = (uint32_t)((u[j] >> ish) - lo), bit = 1u << (b & 31);
+                if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
+            }
+        }
+        __syncthreads();
+        // survivors go to a[ph(0..)], which lies below the repeated bitmap
+        // (the seen bitmap is no longer read)
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            const uint32_t b = (uint32_t)((u[j] >> ish) - lo);
+            const bool keep = (uint32_t)j * NT + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
+            const uint64_t m = ballot(keep);
+            if (m) {
+                uint32_t base = 0;
+                if (lane_id() == 0) base = atomicAdd(&red[RED_CAND], (uint32_t)__builtin_popcountll(m));
+                base = __shfl(base, 0);
+                const uint32_t pos = base + mbcnt(m);
+                if (keep && pos < FILTER_CAP) a[ph(pos)] = u[j];
+            }
+        }
+        __syncthreads();
+        const uint32_t nc = red[RED_CAND];
+        if (nc <= FILTER_CAP) {
+            if (nc == 0) return false;
+            uint32_t np = NT;
+            while (np < nc) np <<= 1;
+            for (uint32_t k = nc + threadIdx.x; k < np; k += NT) a[ph(k)] = ~0ull;
+            n_sort = np;
+            cnt_sort = nc;
+            filtered = true;
+        }
+        // otherwise every thread has read nc and no bitmap is read again:
+        // the whole group is sorted
+    }
+    if (!filtered) {
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            const uint32_t i = (uint32_t)j * NT + threadIdx.x;
+            a[ph(i)] = i < cnt ? u[j] : ~0ull;
+        }
+    }
+    __syncthreads();
+    return sort_scan<NT>(a, n_sort, cnt_sort, tb, red, key, i1, i2);
+}
+
 // =============================================================== fused path
 constexpr uint32_t FN_CACHE = 16;
 // One workgroup per unit: for every phase of the unit (small phases only),
@@ -867,6 +1091,125 @@ struct FusedSink {
     }
 };
 
+// Fused groups of at most FUSED_PACK events are decided with their records
+// left in LDS: they occupy a[0 .. ph(FUSED_PACK)) and the rest of the
+// TILE_LDS array is scratch for
+// the table (LDS_TBL_CELLS cells) or the filter bitmaps (spans up to
+// 2^LDS_FILTER_BITS).  The records are never overwritten before the last
+// method is chosen, so nothing has to stay in registers.
+constexpr uint32_t LDS_SOFF = FUSED_PACK + FUSED_PACK / 32;           // first scratch u64 (= ph(FUSED_PACK))
+constexpr uint32_t LDS_SWORDS = 2 * (TILE_LDS - LDS_SOFF);            // scratch u32 words
+constexpr uint32_t LDS_TBL_CELLS = LDS_SWORDS / 3;
+constexpr uint32_t LDS_FILTER_BITS = 17;
+constexpr uint32_t LDS_FWORDS = 1u << (LDS_FILTER_BITS - 5);
+constexpr uint32_t LDS_FCAP = LDS_FWORDS / 2;                         // survivors held in the seen bitmap's words
+static_assert(2 * LDS_FWORDS <= LDS_SWORDS, "fused filter bitmaps exceed the scratch");
+static_assert(LDS_FCAP <= FUSED_PACK, "fused filter survivors exceed a group");
+
+template <int NT>
+DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t tb, uint32_t *red,
+                    unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+    const uint32_t ish = tb + 1;
+    const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
+    uint32_t *sw = reinterpret_cast<uint32_t *>(a + LDS_SOFF);
+    unsigned long long lo = ~0ull, hi = 0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+        const unsigned long long x = a[ph(i)] >> ish;
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    lo = block_ext64<false>(lo, red);
+    hi = block_ext64<true>(hi, red);
+    const unsigned long long span = hi - lo + 1;   // cells are below 2^63
+
+    if (span <= LDS_TBL_CELLS) {
+        const uint32_t sp = (uint32_t)span;
+        uint32_t *t0 = sw, *w0 = sw + sp, *t1 = sw + 2 * sp;
+        for (uint32_t k = threadIdx.x; k < 3 * sp; k += NT) sw[k] = NONE32;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+            const unsigned long long r = a[ph(i)];
+            const uint32_t b = (uint32_t)((r >> ish) - lo), tid = (uint32_t)(r >> 1) & tmask;
+            atomicMin(&t0[b], tid);
+            if (r & 1ull) atomicMin(&w0[b], tid);
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+            const unsigned long long r = a[ph(i)];
+            const uint32_t b = (uint32_t)((r >> ish) - lo), tid = (uint32_t)(r >> 1) & tmask;
+            if (tid != t0[b]) atomicMin(&t1[b], tid);
+        }
+        __syncthreads();
+        uint32_t first = NONE32;
+        for (uint32_t k = threadIdx.x; k < sp; k += NT) {
+            if (t1[k] != NONE32 && w0[k] != NONE32) { first = k; break; }
+        }
+        first = block_min(first, red);
+        bool found = false;
+        if (first != NONE32) {
+            found = true;
+            key = lo + first;
+            i1 = t0[first];
+            const uint32_t aw = w0[first];
+            i2 = aw == i1 ? t1[first] : aw;
+        }
+        __syncthreads();   // the table is read before the caller reuses the LDS
+        return found;
+    }
+
+    uint32_t n_sort = npow, cnt_sort = cnt;
+    if (span <= (1ull << LDS_FILTER_BITS)) {
+        const uint32_t nw = (uint32_t)((span + 31) >> 5);
+        uint32_t *seen = sw, *rep = sw + LDS_FWORDS;
+        unsigned long long *surv = reinterpret_cast<unsigned long long *>(seen);
+        for (uint32_t k = threadIdx.x; k < nw; k += NT) {
+            seen[k] = 0;
+            rep[k] = 0;
+        }
+        if (threadIdx.x == 0) red[RED_CAND] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+            const uint32_t b = (uint32_t)((a[ph(i)] >> ish) - lo), bit = 1u << (b & 31);
+            if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
+        }
+        __syncthreads();
+        // survivors go to the seen bitmap's words (no longer read)
+        for (uint32_t i0 = 0; i0 < cnt; i0 += NT) {
+            const uint32_t i = i0 + threadIdx.x;
+            unsigned long long r = 0;
+            bool keep = false;
+            if (i < cnt) {
+                r = a[ph(i)];
+                const uint32_t b = (uint32_t)((r >> ish) - lo);
+                keep = ((rep[b >> 5] >> (b & 31)) & 1u) != 0;
+            }
+            const uint64_t m = ballot(keep);
+            if (m) {
+                uint32_t base = 0;
+                if (lane_id() == 0) base = atomicAdd(&red[RED_CAND], (uint32_t)__builtin_popcountll(m));
+                base = __shfl(base, 0);
+                const uint32_t pos = base + mbcnt(m);
+                if (keep && pos < LDS_FCAP) surv[pos] = r;
+            }
+        }
+        __syncthreads();
+        const uint32_t nc = red[RED_CAND];
+        if (nc == 0) return false;
+        if (nc <= LDS_FCAP) {
+            uint32_t np = NT;
+            while (np < nc) np <<= 1;
+            for (uint32_t k = threadIdx.x; k < np; k += NT) a[ph(k)] = k < nc ? surv[k] : ~0ull;
+            n_sort = np;
+            cnt_sort = nc;
+        }
+        // otherwise the group's records are still in place: all are sorted
+    }
+    if (cnt_sort == cnt)
+        for (uint32_t k = cnt + threadIdx.x; k < npow; k += NT) a[ph(k)] = ~0ull;
+    __syncthreads();
+    return sort_scan<NT>(a, n_sort, cnt_sort, tb, red, key, i1, i2);
+}
+
 template <typename T, bool WIDE>
 DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
                     const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,
@@ -876,7 +1219,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     uint32_t tile) {
     __shared__ unsigned long long lds_rec[TILE_LDS];
     __shared__ uint32_t lds_n;
-    __shared__ uint32_t lds_res[20];
+    __shared__ uint32_t lds_res[RED_WORDS];
     __shared__ uint32_t lds_unit;
     __shared__ uint32_t lds_ovf;
     // per wave: the next unprocessed iteration of each of the protocol's
@@ -923,7 +1266,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 } else {
                     c = pd.phase_bound;
                 }
-                if (any && (!pack || est + c > (uint32_t)TILE)) break;
+                if (any && (!pack || est + c > (uint32_t)FUSED_PACK)) break;
                 const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
                 for (uint32_t ni = 0; ni < pd.nnests; ni++) {
                     const NestDesc &nd = nests[pd.nest0 + ni];
@@ -971,14 +1314,19 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 __syncthreads();
                 continue;
             }
-            uint32_t npow = 256;
+            uint32_t npow = WG;
             while (npow < cnt) npow <<= 1;
-            for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[ph(i)] = ~0ull;
-            __syncthreads();
-            block_sort(lds_rec, npow);
-            unsigned long long key;
-            uint32_t r1, r2;
-            const bool f = block_first_racy(lds_rec, cnt, tb, lds_res, key, r1, r2);
+            unsigned long long key = 0;
+            uint32_t r1 = 0, r2 = 0;
+            bool f;
+            if (npow <= (uint32_t)FUSED_PACK) {
+                f = decide_lds<WG>(lds_rec, cnt, npow, tb, lds_res, key, r1, r2);
+            } else {
+                // one phase above FUSED_PACK events: sorted and scanned whole
+                for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[ph(i)] = ~0ull;
+                __syncthreads();
+                f = sort_scan<WG>(lds_rec, npow, cnt, tb, lds_res, key, r1, r2);
+            }
             if (f && !have) {
                 have = true;
                 const uint64_t kk = gk0 + (pack ? (key >> pd.ib) : 0ull);
@@ -1074,83 +1422,13 @@ __global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const uns
 }
 
 // ================================================================== tiles
-DEV uint32_t wave_min(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w < v ? w : v; }
-    return v;
-}
-DEV uint32_t wave_max(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) { uint32_t w = __shfl_xor(v, o); v = w > v ? w : v; }
-    return v;
-}
-// Workgroup min / max through red[0 .. waves) (barriers on entry and exit).
-DEV uint32_t block_min(uint32_t v, uint32_t *red) {
-    v = wave_min(v);
-    __syncthreads();
-    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint32_t r = red[0];
-    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) r = red[w] < r ? red[w] : r;
-    __syncthreads();
-    return r;
-}
-DEV uint32_t block_max(uint32_t v, uint32_t *red) {
-    v = wave_max(v);
-    __syncthreads();
-    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint32_t r = red[0];
-    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) r = red[w] > r ? red[w] : r;
-    __syncthreads();
-    return r;
-}
-
-// A tile is decided by one of three methods, chosen from the index span of
-// its records (all of one phase):
-//  table   span <= TBL_CELLS: per index cell, the least tid, the least
-//          writing tid and the least tid other than the first, by LDS
-//          atomics.  Definition 1 needs nothing else: the cell races iff a
-//          second tid and a writer exist, and the witness is (least tid,
-//          least other tid if the least tid writes, else least writer).
-//  filter  span <= 2^FILTER_BITS: a seen / repeated bitmap pair removes
-//          every index touched by a single record (one access cannot race);
-//          the records left are sorted and scanned.
-//  sort    otherwise, or when more than FILTER_CAP records survive the
-//          filter: the whole tile is sorted and scanned.
-// Tiles run 512-thread workgroups: at most 16 records per thread stay in
-// registers, and the two workgroups the LDS admits per CU give 4 waves per
-// SIMD.
-constexpr int TWG = 512;
-constexpr uint32_t TBL_CELLS = (TILE_LDS * 2) / 3;       // three u32 per cell
-constexpr uint32_t FILTER_WORDS = 1u << (FILTER_BITS - 5);
-constexpr uint32_t FILTER_CAP = 3968;                    // ph() slots below the repeated bitmap
-static_assert(2 * FILTER_WORDS <= 2 * TILE_LDS, "filter bitmaps exceed the tile LDS");
-static_assert(FILTER_CAP - 1 + (FILTER_CAP - 1) / 32 < FILTER_WORDS / 2, "filter output overlaps its bitmap");
-static_assert(TILE % TWG == 0 && TILE / TWG <= 16, "tile records per thread");
-constexpr uint32_t RED_CAND = 5 * (TWG / 64);            // candidate counter, after the scan's slots
-constexpr uint32_t RED_WORDS = RED_CAND + 1;
-
-// Sorts a[0..n) (n a power of two, TWG <= n <= TILE) with a TWG-thread
-// workgroup and returns the first racy group of its cnt records.
-DEV bool tile_sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t *red, unsigned long long &key,
-                        uint32_t &i1, uint32_t &i2) {
-    switch (n / TWG) {
-    case 1: block_sort_e<1, TWG>(a, n); break;
-    case 2: block_sort_e<2, TWG>(a, n); break;
-    case 4: block_sort_e<4, TWG>(a, n); break;
-    case 8: block_sort_e<8, TWG>(a, n); break;
-    default: block_sort_e<16, TWG>(a, n); break;
-    }
-    return block_first_racy(a, cnt, 31, red, key, i1, i2);
-}
-
-// Records are read straight into registers (element i = j * TWG + tid, all
-// loads issued before any use; lanes past the end re-read the last record,
-// so no branch sits between the loads).
+// Tile records are read straight into registers (all loads issued before
+// any use; lanes past the end re-read the last record, so no branch sits
+// between the loads).
 template <int E>
 DEV void tile_run(const Tile &t, const unsigned long long *__restrict__ src, unsigned long long *a, uint32_t *red,
                   Cand *my, Best *best) {
     const uint32_t cnt = t.len;
-    uint32_t *w32 = reinterpret_cast<uint32_t *>(a);
     unsigned long long u[E];
     const uint32_t last = cnt - 1;
 #pragma unroll
@@ -1158,111 +1436,10 @@ DEV void tile_run(const Tile &t, const unsigned long long *__restrict__ src, uns
         const uint32_t i = (uint32_t)j * TWG + threadIdx.x;
         u[j] = src[i < cnt ? i : last];
     }
-    uint32_t lo = NONE32, hi = 0;
-#pragma unroll
-    for (int j = 0; j < E; j++) {
-        const uint32_t x = rec_idx(u[j]);
-        lo = x < lo ? x : lo;
-        hi = x > hi ? x : hi;
-    }
-    lo = block_min(lo, red);
-    hi = block_max(hi, red);
-    const uint64_t span = (uint64_t)hi - lo + 1;
-
-    if (span <= TBL_CELLS) {
-        const uint32_t sp = (uint32_t)span;
-        uint32_t *t0 = w32, *w0 = w32 + sp, *t1 = w32 + 2 * sp;
-        for (uint32_t k = threadIdx.x; k < 3 * sp; k += TWG) w32[k] = NONE32;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((uint32_t)j * TWG + threadIdx.x < cnt) {
-                const uint32_t b = rec_idx(u[j]) - lo, tid = rec_tid(u[j]);
-                atomicMin(&t0[b], tid);
-                if (u[j] & 1ull) atomicMin(&w0[b], tid);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((uint32_t)j * TWG + threadIdx.x < cnt) {
-                const uint32_t b = rec_idx(u[j]) - lo, tid = rec_tid(u[j]);
-                if (tid != t0[b]) atomicMin(&t1[b], tid);
-            }
-        }
-        __syncthreads();
-        uint32_t first = NONE32;
-        for (uint32_t k = threadIdx.x; k < sp; k += TWG) {
-            if (t1[k] != NONE32 && w0[k] != NONE32) { first = k; break; }
-        }
-        first = block_min(first, red);
-        if (first != NONE32 && threadIdx.x == 0) {
-            const uint32_t a0 = t0[first], aw = w0[first];
-            offer(best, my, t.proto, t.phase, lo + first, a0, aw == a0 ? t1[first] : aw);
-        }
-        return;
-    }
-
-    if (span <= (1ull << FILTER_BITS)) {
-        const uint32_t nw = (uint32_t)((span + 31) >> 5);
-        uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
-        for (uint32_t k = threadIdx.x; k < nw; k += TWG) {
-            seen[k] = 0;
-            rep[k] = 0;
-        }
-        if (threadIdx.x == 0) red[RED_CAND] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((uint32_t)j * TWG + threadIdx.x < cnt) {
-                const uint32_t b = rec_idx(u[j]) - lo, bit = 1u << (b & 31);
-                if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
-            }
-        }
-        __syncthreads();
-        // survivors go to a[ph(0..)], which lies below the repeated bitmap
-        // (the seen bitmap is no longer read)
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            const uint32_t b = rec_idx(u[j]) - lo;
-            const bool keep = (uint32_t)j * TWG + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
-            const uint64_t m = ballot(keep);
-            if (m) {
-                uint32_t base = 0;
-                if (lane_id() == 0) base = atomicAdd(&red[RED_CAND], (uint32_t)__builtin_popcountll(m));
-                base = __shfl(base, 0);
-                const uint32_t pos = base + mbcnt(m);
-                if (keep && pos < FILTER_CAP) a[ph(pos)] = u[j];
-            }
-        }
-        __syncthreads();
-        const uint32_t nc = red[RED_CAND];
-        if (nc <= FILTER_CAP) {
-            if (nc == 0) return;
-            uint32_t np = TWG;
-            while (np < nc) np <<= 1;
-            for (uint32_t k = nc + threadIdx.x; k < np; k += TWG) a[ph(k)] = ~0ull;
-            __syncthreads();
-            uint32_t r1, r2;
-            unsigned long long rkey;
-            const bool f = tile_sort_scan(a, np, nc, red, rkey, r1, r2);
-            if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)rkey, r1, r2);
-            return;
-        }
-        // every thread has read nc and no bitmap is read again: the whole
-        // tile is sorted below
-    }
-
-#pragma unroll
-    for (int j = 0; j < E; j++) {
-        const uint32_t i = (uint32_t)j * TWG + threadIdx.x;
-        a[ph(i)] = i < cnt ? u[j] : ~0ull;
-    }
-    __syncthreads();
+    unsigned long long key;
     uint32_t r1, r2;
-    unsigned long long rkey;
-    const bool f = tile_sort_scan(a, (uint32_t)TWG * E, cnt, red, rkey, r1, r2);
-    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)rkey, r1, r2);
+    const bool f = decide<E, TWG>(u, cnt, 31, a, red, key, r1, r2);
+    if (f && threadIdx.x == 0) offer(best, my, t.proto, t.phase, (uint32_t)key, r1, r2);
 }
 
 // two workgroups per CU fit the LDS: ask for the registers of four waves per SIMD
