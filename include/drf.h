@@ -207,7 +207,8 @@ uint64_t drf_prepared_launches(const drf_prepared *p);
 
 /* Tuning of a context (what the autotuner sets).  tile_events: most access
  * events of one phase (or bucket) sorted in one LDS tile, a power of two in
- * [256, 8192]; digit_bits: index bits per MSD partition level, 4..10;
+ * [256, 8192]; digit_bits: the most index bits of one MSD partition level,
+ * 4..10 (a level takes fewer for a short segment);
  * unit_events / item_events: target events per fused unit / per count and
  * emit work item.  Zero fields keep their value; DRF_E_ARG when out of
  * range (nothing changes then). */

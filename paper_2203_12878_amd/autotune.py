@@ -3,7 +3,7 @@
 For a workload (a prepared Batch) it measures full checks under candidate
 tunings by coordinate descent over
     tile_events  (events sorted in one LDS tile / fused-path threshold)
-    digit_bits   (index bits per MSD partition level)
+    digit_bits   (most index bits of one MSD partition level)
     unit_events  (events per fused unit)
     item_events  (events per count / emit work item)
 and keeps the fastest.  Results are cached per size class of the workload
@@ -26,7 +26,7 @@ SPACE = {
     "unit_events": [4096, 16384, 65536, 262144],
     "item_events": [1 << 14, 1 << 16, 1 << 18],
 }
-DEFAULT = {"tile_events": 8192, "digit_bits": 8, "unit_events": 1 << 16, "item_events": 1 << 16}
+DEFAULT = {"tile_events": 8192, "digit_bits": 10, "unit_events": 1 << 16, "item_events": 1 << 16}
 CACHE = os.environ.get("DRF_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "drf_tuning.json"))
 
 

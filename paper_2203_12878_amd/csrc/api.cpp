@@ -51,7 +51,7 @@ struct drf_ctx {
     hipEvent_t counted = nullptr;
     bool done_valid = false;
     uint32_t cus = 256;
-    drf_tuning tune = {(uint32_t)drf::TILE, 8, 1u << 16, 1u << 16};
+    drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 16, 1u << 16};
     // per-kernel-class timing
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -485,6 +485,15 @@ WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t ni
     return L;
 }
 
+// Index bits of one partition level for a segment of len records: buckets
+// of about 512 records on average (skewed index distributions then still
+// fit tiles in one level), at least 4 bits, at most the tuned maximum.
+uint32_t digit_bits_for(uint64_t len, uint32_t max_bits) {
+    uint32_t b = 4;
+    while (b < max_bits && (len >> b) > 512) b++;
+    return b;
+}
+
 struct Wave {
     size_t bi, be;
     uint64_t recs;
@@ -609,7 +618,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         sg.len = big[j].count;
         sg.proto = big[j].proto;
         sg.phase = big[j].local;
-        sg.dbits = std::min<uint32_t>(dbits, r);
+        sg.dbits = std::min<uint32_t>(digit_bits_for(sg.len, dbits), r);
         sg.shift = r - sg.dbits;
         segs.push_back(sg);
     }
@@ -620,18 +629,22 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     while (!segs.empty()) {
         std::vector<Chunk> chunks;
         std::vector<uint64_t> out_start(segs.size());
-        uint64_t hb = 0, op = 0;
+        uint64_t hb = 0, op = 0, nstarts = 0;
         for (size_t s2 = 0; s2 < segs.size(); s2++) {
             Seg &sg = segs[s2];
             sg.nchunks = (uint32_t)((sg.len + CHUNK - 1) / CHUNK);
             sg.hbase = hb;
             hb += (uint64_t)sg.nchunks << sg.dbits;
+            sg.sbase = (uint32_t)nstarts;
+            nstarts += 1ull << sg.dbits;
             out_start[s2] = op;
             op += sg.len;
             for (uint32_t c = 0; c < sg.nchunks; c++) chunks.push_back(Chunk{(uint32_t)s2, c});
         }
         // the level must fit the regions the wave layout reserved
-        if (segs.size() > L.nsegs_max || chunks.size() > L.chunks_max || hb > L.hist_max) throw Fail{DRF_E_NOMEM};
+        if (segs.size() > L.nsegs_max || chunks.size() > L.chunks_max || hb > L.hist_max ||
+            nstarts > L.nsegs_max * sstride || nstarts > 0xFFFFFFFFull)
+            throw Fail{DRF_E_NOMEM};
         const Seg *dsegs = C.put(at<void>(B, L.o_segs), segs);
         const Chunk *dch = C.put(at<void>(B, L.o_chunks), chunks);
         const uint32_t nch = (uint32_t)chunks.size(), nsg = (uint32_t)segs.size();
@@ -651,9 +664,9 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         }
         {
             Prof pr(ctx, st, K_OTHER, 0, 0);
-            C.dev([=](hipStream_t s) { return launch_starts(dsegs, nsg, hist, dstarts, sstride, s); });
+            C.dev([=](hipStream_t s) { return launch_starts(dsegs, nsg, hist, dstarts, s); });
         }
-        std::vector<uint64_t> starts(segs.size() * sstride);
+        std::vector<uint64_t> starts(nstarts);
         hipck(hipMemcpyAsync(starts.data(), dstarts, starts.size() * 8, hipMemcpyDeviceToHost, st));
         C.sync();
         C.tr.mark("level partitioned", segs.size());
@@ -672,8 +685,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             uint32_t cur_d0 = 0;
             const bool span_cap = sg.shift < FILTER_BITS;
             for (uint32_t d = 0; d < nd; d++) {
-                const uint64_t a0 = starts[s2 * sstride + d];
-                const uint64_t e = (d + 1 < nd) ? starts[s2 * sstride + d + 1] : out_start[s2] + sg.len;
+                const uint64_t a0 = starts[sg.sbase + d];
+                const uint64_t e = (d + 1 < nd) ? starts[sg.sbase + d + 1] : out_start[s2] + sg.len;
                 const uint64_t len = e - a0;
                 if (len == 0) continue;
                 if (len <= (uint64_t)tile) {
@@ -697,7 +710,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
                     ns.len = len;
                     ns.proto = sg.proto;
                     ns.phase = sg.phase;
-                    ns.dbits = std::min<uint32_t>(dbits, sg.shift);
+                    ns.dbits = std::min<uint32_t>(digit_bits_for(len, dbits), sg.shift);
                     ns.shift = sg.shift - ns.dbits;
                     next.push_back(ns);
                 }

@@ -436,6 +436,31 @@ struct EmitSink {
 constexpr uint32_t CAL_U = 2048;    // staged uniform values per chunk
 constexpr uint32_t CAL_CH = 256;    // iterations per chunk
 
+// Runs the chain of one compiled access on tid; uniform slot z reads
+// U[z * ustride].
+DEV uint32_t cal_chain(const uint32_t *__restrict__ ap, uint32_t nops, uint32_t tid, const uint32_t *U,
+                       uint32_t ustride) {
+    uint32_t v = tid;
+    for (uint32_t o = 0; o < nops; o++) {
+        const uint32_t opw = rfl(ap[2 * o]), arg = rfl(ap[2 * o + 1]);
+        const uint32_t x = (opw & C_UNI) ? rfl(U[arg * ustride]) : arg;
+        switch (opw & 0xFFu) {
+        case C_ADD: v += x; break;
+        case C_MUL: v *= x; break;
+        case C_MONUS: v = v > x ? v - x : 0u; break;
+        case C_RMONUS: v = x > v ? x - v : 0u; break;
+        case C_DIV: v = x ? v / x : 0u; break;
+        case C_MOD: v = x ? v % x : v; break;
+        case C_SHL: v = x >= 32u ? 0u : v << x; break;
+        case C_SHR: v = x >= 32u ? 0u : v >> x; break;
+        case C_MIN: v = v < x ? v : x; break;
+        case C_MAX: v = v > x ? v : x; break;
+        default: v &= x; break;   // C_AND
+        }
+    }
+    return v;
+}
+
 struct CalLds {
     uint32_t u[CAL_U];
     uint32_t ph[CAL_CH];
@@ -499,25 +524,7 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
             const uint32_t *ap = acc0;
             for (uint32_t j = 0; j < nacc; j++) {
                 const uint32_t mode = rfl(ap[0]), nops = rfl(ap[1]);
-                uint32_t v = tid;
-                for (uint32_t o = 0; o < nops; o++) {
-                    const uint32_t opw = rfl(ap[2 + 2 * o]), arg = rfl(ap[3 + 2 * o]);
-                    const uint32_t x = (opw & C_UNI) ? rfl(L.u[arg * chp + i]) : arg;
-                    switch (opw & 0xFFu) {
-                    case C_ADD: v += x; break;
-                    case C_MUL: v *= x; break;
-                    case C_MONUS: v = v > x ? v - x : 0u; break;
-                    case C_RMONUS: v = x > v ? x - v : 0u; break;
-                    case C_DIV: v = x ? v / x : 0u; break;
-                    case C_MOD: v = x ? v % x : v; break;
-                    case C_SHL: v = x >= 32u ? 0u : v << x; break;
-                    case C_SHR: v = x >= 32u ? 0u : v >> x; break;
-                    case C_MIN: v = v < x ? v : x; break;
-                    case C_MAX: v = v > x ? v : x; break;
-                    default: v &= x; break;   // C_AND
-                    }
-                }
-                sink.acc(act, v, mode);
+                sink.acc(act, cal_chain(ap + 2, nops, tid, L.u + i, chp), mode);
                 ap += 2 + 2 * nops;
             }
         }
@@ -1210,6 +1217,20 @@ DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t
     return sort_scan<NT>(a, n_sort, cnt_sort, tb, red, key, i1, i2);
 }
 
+// Compiled leaves in the fused kernel: at the start of a unit the
+// workgroup evaluates, for the iterations the unit covers of each of the
+// first FN_CACHE nests (as far as STAGE_WORDS allow), the phase, the thread
+// limit and every uniform slot, one iteration per lane.  Each phase then
+// only runs the lanes' access chains.
+constexpr uint32_t STAGE_WORDS = 2048;
+struct FusedStage {
+    uint32_t base[FN_CACHE];            // first word of the nest's block in w, or NONE32 (not staged)
+    uint32_t cnt[FN_CACHE];             // staged iterations
+    uint32_t acc[FN_CACHE];             // word offset of the access blocks in the compiled leaf
+    unsigned long long f0[FN_CACHE];    // first staged iteration
+    uint32_t w[STAGE_WORDS];            // per nest: phase - k0, thread limit, then each slot (cnt words each)
+};
+
 template <typename T, bool WIDE>
 DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
                     const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,
@@ -1225,6 +1246,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
     // per wave: the next unprocessed iteration of each of the protocol's
     // first FN_CACHE nests (each wave reads only its own row: no barrier)
     __shared__ unsigned long long lds_nf[WG / 64][FN_CACHE];
+    __shared__ FusedStage lds_st;
     unsigned long long *nf = lds_nf[threadIdx.x >> 6];
     // persistent: workgroups pull units (largest first) from a device queue
     for (;;) {
@@ -1249,6 +1271,55 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
         const uint32_t psh = pack ? pd.ib + tb + 1 : 64u;   // phase-in-group shift
         const uint32_t ncache = pd.nnests < FN_CACHE ? pd.nnests : FN_CACHE;
         for (uint32_t ni = lane_id(); ni < ncache; ni += 64) nf[ni] = first_iter_at(nests[pd.nest0 + ni], u.k0);
+        if constexpr (!WIDE) {
+            if (threadIdx.x == 0) {
+                uint32_t off = 0;
+                for (uint32_t ni = 0; ni < ncache; ni++) {
+                    const NestDesc &nd = nests[pd.nest0 + ni];
+                    lds_st.base[ni] = NONE32;
+                    if (nd.cal_off == NONE32 || u.k1 <= nd.phase_base || u.k0 > nd.phase_last) continue;
+                    const uint64_t fa = first_iter_at(nd, u.k0), fb = first_iter_at(nd, u.k1);
+                    if (fb <= fa) continue;
+                    const uint32_t *cal = code + nd.cal_off;
+                    const uint32_t nuni = cal[1];
+                    const uint64_t need = (2 + (uint64_t)nuni) * (fb - fa);
+                    if (off + need > STAGE_WORDS) continue;
+                    uint32_t o = 2;
+                    for (uint32_t z = 0; z < nuni; z++) o += 1 + cal[o];
+                    lds_st.base[ni] = off;
+                    lds_st.cnt[ni] = (uint32_t)(fb - fa);
+                    lds_st.acc[ni] = o;
+                    lds_st.f0[ni] = fa;
+                    off += (uint32_t)need;
+                }
+            }
+            __syncthreads();
+            for (uint32_t ni = 0; ni < ncache; ni++) {
+                const uint32_t sb = lds_st.base[ni];
+                if (sb == NONE32) continue;
+                const NestDesc &nd = nests[pd.nest0 + ni];
+                const uint32_t cs = lds_st.cnt[ni];
+                const uint32_t *cal = code + nd.cal_off;
+                const uint32_t nuni = rfl(cal[1]);
+                for (uint32_t fi = threadIdx.x; fi < cs; fi += WG) {
+                    T vars[MAXSLOTS];
+                    for (int z = 0; z < MAXSLOTS; z++) vars[z] = 0;
+                    load_fixed<T>(nd, fixed, vars);
+                    Odo<T> odo;
+                    odo.start(nd, lds_st.f0[ni] + fi, vars);
+                    lds_st.w[sb + fi] = (uint32_t)(odo.phase - u.k0);
+                    lds_st.w[sb + cs + fi] = tid_limit<T>(nd, code, vars, pd.n);
+                    const uint32_t *up = cal + 2;
+                    for (uint32_t z = 0; z < nuni; z++) {
+                        bool o = false;
+                        const uint32_t len = rfl(up[0]);
+                        lds_st.w[sb + (2 + z) * cs + fi] = (uint32_t)eval_expr<T, false>(up + 1, len, vars, (T)0, o);
+                        up += 1 + len;
+                    }
+                }
+            }
+            __syncthreads();
+        }
         uint64_t k = u.k0;
         while (k < u.k1) {
             // one group of consecutive phases whose events fit one tile
@@ -1271,6 +1342,35 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 for (uint32_t ni = 0; ni < pd.nnests; ni++) {
                     const NestDesc &nd = nests[pd.nest0 + ni];
                     if (k < nd.phase_base || k > nd.phase_last) continue;
+                    if constexpr (!WIDE) {
+                        const uint32_t sb = ni < ncache ? lds_st.base[ni] : NONE32;
+                        if (sb != NONE32) {
+                            const uint32_t cs = lds_st.cnt[ni];
+                            const uint32_t kr = (uint32_t)(k - u.k0);
+                            uint32_t i = (uint32_t)(nf[ni] - lds_st.f0[ni]);
+                            while (i < cs && rfl(lds_st.w[sb + i]) < kr) i++;   // phases skipped since
+                            const uint32_t *cal = code + nd.cal_off;
+                            const uint32_t nacc = rfl(cal[0]);
+                            const uint32_t *acc0 = cal + rfl(lds_st.acc[ni]);
+                            for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
+                                const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
+                                const uint32_t *U = lds_st.w + sb + 2 * cs + i;
+                                for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
+                                    const uint32_t tid = t0 + threadIdx.x;
+                                    const bool act = tid < pd.n && tid < lim;
+                                    FusedSink sink{lds_rec, &lds_n, pre, ish, tid};
+                                    const uint32_t *ap = acc0;
+                                    for (uint32_t j = 0; j < nacc; j++) {
+                                        const uint32_t mode = rfl(ap[0]), nops = rfl(ap[1]);
+                                        sink.acc(act, cal_chain(ap + 2, nops, tid, U, cs), mode);
+                                        ap += 2 + 2 * nops;
+                                    }
+                                }
+                            }
+                            nf[ni] = lds_st.f0[ni] + i;
+                            continue;
+                        }
+                    }
                     // the cached iteration is the first of phase k unless
                     // phases were skipped since (then search again)
                     uint64_t fa = ni < ncache ? nf[ni] : first_iter_at(nd, k);
@@ -1409,16 +1509,16 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
     }
 }
 
-// starts[s * 256 + d] = first output position of digit d of segment s
+// starts[sbase + d] = first output position of digit d of segment s
 // (the end of the last digit is the end of the segment's output).
 __global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const unsigned long long *__restrict__ offs,
-                         unsigned long long *__restrict__ starts, uint32_t stride) {
+                         unsigned long long *__restrict__ starts) {
     const uint32_t s = blockIdx.x;
     if (s >= nsegs) return;
     const Seg sg = segs[s];
     const uint32_t nd = 1u << sg.dbits;
     for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x)
-        starts[(uint64_t)s * stride + d] = offs[sg.hbase + (uint64_t)d * sg.nchunks];
+        starts[(uint64_t)sg.sbase + d] = offs[sg.hbase + (uint64_t)d * sg.nchunks];
 }
 
 // ================================================================== tiles
@@ -1684,8 +1784,8 @@ hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks
 }
 
 hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs, unsigned long long *starts,
-                         uint32_t stride, hipStream_t s) {
-    return launch(k_starts, dim3(nsegs), dim3(256), s, segs, nsegs, offs, starts, stride);
+                         hipStream_t s) {
+    return launch(k_starts, dim3(nsegs), dim3(256), s, segs, nsegs, offs, starts);
 }
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands, Best *best,

@@ -25,7 +25,7 @@ struct Seg {
     uint32_t phase;       // local phase
     uint32_t shift;       // digit = (index >> shift) & (2^dbits - 1)
     uint32_t dbits;
-    uint32_t pad;
+    uint32_t sbase;       // first of the segment's 2^dbits bucket starts
 };
 
 struct Chunk {
@@ -86,7 +86,7 @@ hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks
                           hipStream_t s);
 
 hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs,
-                         unsigned long long *starts, uint32_t stride, hipStream_t s);
+                         unsigned long long *starts, hipStream_t s);
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands,
                         Best *best, hipStream_t s);
