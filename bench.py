@@ -28,6 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# bytes per record the method must move with records materialized in HBM
+# (one 8-byte record write, its read-back by the conflict pass, and the
+# 8-byte histogram read of one partition level)
+EFFECTIVE_BYTES_PER_RECORD = 24
 # integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one 32-bit op per lane per clock)
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
@@ -85,6 +89,78 @@ def kernel_stats(lib, ctx, reset=True):
             for a in arr[:n.value]}
 
 
+def kernels_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "drf_layout.hpp"):
+        with open(os.path.join(ROOT, "paper_2203_12878_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when none exists or the kernels have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^- (\w+): `?([^`\s]+)`?", line.strip())
+            if m:
+                vals[m.group(1)] = m.group(2)
+    if vals.get("kernels_sha256") != kernels_sha256():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def compare_paths(drf, chk):
+    """Batched (one check over the whole set) against plain (one protocol
+    per call) on a sample of the batched workloads."""
+    import torch
+    from paper_2203_12878_amd import workloads as w
+    items = [(t, n) for t, n, _ in w.gen_mixed_batch(0, 512)] + [(t, n) for t, n, _ in w.gen_tree_batch(0, 128)]
+    batch = drf.Batch(items, 0)
+    out = {}
+    for name, run in (("batched", chk.run_batch), ("plain", chk.run_plain)):
+        run(batch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            run(batch)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) / reps
+    recs = sum(r.num_records for r in batch.collect())
+    return {"sample": "first 512 protocols of the mixed batch and first 128 tree instances (seed 0), %d records" % recs,
+            "batched_records_per_s": round(recs / out["batched"], 1), "plain_records_per_s": round(recs / out["plain"], 1),
+            "batched_ms": round(out["batched"] * 1e3, 3), "plain_ms": round(out["plain"] * 1e3, 3),
+            "speedup": round(out["plain"] / out["batched"], 3)}
+
+
+def serving(rates, horizon_s=1.0):
+    """Poisson streams of check requests through the continuous-batching
+    server: latency percentiles and throughput per offered rate."""
+    from paper_2203_12878_amd import workloads as w
+    from paper_2203_12878_amd.server import Server, run_stream
+    rows = []
+    for rate in rates:
+        reqs = w.gen_requests(rate=float(rate), max_requests=int(rate * horizon_s * 2), horizon_s=horizon_s)
+        with Server(device=0, workers=2, budget_bytes=8 << 30) as srv:
+            res, wall = run_stream(srv, reqs)
+            st = srv.stats
+        recs = sum(r.num_records for r in res)
+        rows.append({"offered_req_per_s": rate, "requests": len(reqs), "p50_ms": round(st.percentile(50) * 1e3, 3),
+                     "p99_ms": round(st.percentile(99) * 1e3, 3), "records_per_s": round(recs / wall, 1),
+                     "req_per_s": round(len(reqs) / wall, 1), "batches": st.batches})
+    return rows
+
+
 def cpu_baseline(items, records_per_step):
     """The C oracle on the same protocols, on host cores."""
     from oracle import o2
@@ -108,6 +184,7 @@ def main():
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--unit-events", type=int, default=0)
     ap.add_argument("--item-events", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched-vs-plain and serving sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build checks protocols on one GPU; --gpus %d is not supported "
@@ -163,7 +240,8 @@ def main():
     if d["bytes"] > 0:
         achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9
         roof = {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": committed_traffic(dname, args.workload),
                 "bytes_per_launch": d["bytes"] // launches, "avg_launch_ms": round(avg_ms, 4)}
     else:
         ops = expr_ops(items[0][0]) if len(items) == 1 else 1
@@ -189,6 +267,7 @@ def main():
                    "records_per_step": records, "racy_protocols": racy, "tuning": chk.tuning()},
         "parity_vs_stored_oracle": parity,
         "roofline": roof,
+        "effective_hbm_frac": round(value * EFFECTIVE_BYTES_PER_RECORD / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,
                         "records_per_step": v["records"] // args.steps, "bytes_per_step": v["bytes"] // args.steps}
                     for k, v in stats.items() if v["launches"]},
@@ -196,6 +275,9 @@ def main():
     if not args.no_cpu_baseline:
         cb, _ = cpu_baseline(items if len(items) == 1 else items[:64], records)
         line["cpu_baseline"] = cb
+    if not args.no_extras:
+        line["batched_vs_plain"] = compare_paths(drf, chk)
+        line["serving"] = serving([1000, 5000])
     print(json.dumps(line), flush=True)
     chk.close()
 

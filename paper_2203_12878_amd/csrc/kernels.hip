@@ -1474,12 +1474,18 @@ __global__ __launch_bounds__(WG) void k_hist(const Seg *__restrict__ segs, const
     for (uint32_t i = threadIdx.x; i < RADIX; i += WG) h[i] = 0;
     __syncthreads();
     const uint64_t b = sg.start + (uint64_t)ch.c * CHUNK;
-    const uint64_t e = (sg.start + sg.len < b + CHUNK) ? sg.start + sg.len : b + CHUNK;
+    const uint32_t n = (uint32_t)((sg.start + sg.len < b + CHUNK) ? sg.start + sg.len - b : CHUNK);
     const uint32_t mask = (1u << sg.dbits) - 1;
-    for (uint64_t i = b + threadIdx.x; i < e; i += WG) {
-        const uint32_t d = (rec_idx(in[i]) >> sg.shift) & mask;
-        atomicAdd(&h[d], 1u);
+    // all loads of a thread are issued before its first atomic
+    unsigned long long r[CHUNK / WG];
+#pragma unroll
+    for (int j = 0; j < CHUNK / WG; j++) {
+        const uint32_t i = (uint32_t)j * WG + threadIdx.x;
+        r[j] = in[b + (i < n ? i : n - 1)];
     }
+#pragma unroll
+    for (int j = 0; j < CHUNK / WG; j++)
+        if ((uint32_t)j * WG + threadIdx.x < n) atomicAdd(&h[(rec_idx(r[j]) >> sg.shift) & mask], 1u);
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < (1u << sg.dbits); d += WG) hist[sg.hbase + (uint64_t)d * sg.nchunks + ch.c] = h[d];
 }
@@ -1499,13 +1505,21 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
     }
     __syncthreads();
     const uint64_t b = sg.start + (uint64_t)ch.c * CHUNK;
-    const uint64_t e = (sg.start + sg.len < b + CHUNK) ? sg.start + sg.len : b + CHUNK;
+    const uint32_t n = (uint32_t)((sg.start + sg.len < b + CHUNK) ? sg.start + sg.len - b : CHUNK);
     const uint32_t mask = nd - 1;
-    for (uint64_t i = b + threadIdx.x; i < e; i += WG) {
-        const unsigned long long r = in[i];
-        const uint32_t d = (rec_idx(r) >> sg.shift) & mask;
-        const uint32_t o = atomicAdd(&cur[d], 1u);
-        if (base[d] + o < cap) out[base[d] + o] = r;
+    unsigned long long r[CHUNK / WG];
+#pragma unroll
+    for (int j = 0; j < CHUNK / WG; j++) {
+        const uint32_t i = (uint32_t)j * WG + threadIdx.x;
+        r[j] = in[b + (i < n ? i : n - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < CHUNK / WG; j++) {
+        if ((uint32_t)j * WG + threadIdx.x < n) {
+            const uint32_t d = (rec_idx(r[j]) >> sg.shift) & mask;
+            const uint32_t o = atomicAdd(&cur[d], 1u);
+            if (base[d] + o < cap) out[base[d] + o] = r[j];
+        }
     }
 }
 
