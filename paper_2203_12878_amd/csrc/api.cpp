@@ -638,6 +638,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             sg.sbase = (uint32_t)nstarts;
             nstarts += 1ull << sg.dbits;
             out_start[s2] = op;
+            sg.obase = op;
             op += sg.len;
             for (uint32_t c = 0; c < sg.nchunks; c++) chunks.push_back(Chunk{(uint32_t)s2, c});
         }
@@ -655,16 +656,13 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             C.dev([=](hipStream_t s) { return launch_hist(dsegs, dch, nch, cin, hist, s); });
         }
         {
-            Prof pr(ctx, st, K_SCAN, 0, hb * 16);
-            C.dev([=](hipStream_t s) { return launch_scan_u64(hist, hb, hist + hb, s); });
+            // counts in, output positions out (read twice, written once)
+            Prof pr(ctx, st, K_SCAN, 0, hb * 24);
+            C.dev([=](hipStream_t s) { return launch_offsets(dsegs, nsg, hist, dstarts, s); });
         }
         {
             Prof pr(ctx, st, K_SCATTER, op, op * 16);
             C.dev([=](hipStream_t s) { return launch_scatter(dsegs, dch, nch, cin, hist, cout, recs, s); });
-        }
-        {
-            Prof pr(ctx, st, K_OTHER, 0, 0);
-            C.dev([=](hipStream_t s) { return launch_starts(dsegs, nsg, hist, dstarts, s); });
         }
         std::vector<uint64_t> starts(nstarts);
         hipck(hipMemcpyAsync(starts.data(), dstarts, starts.size() * 8, hipMemcpyDeviceToHost, st));

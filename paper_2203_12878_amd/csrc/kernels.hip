@@ -1483,11 +1483,84 @@ __global__ __launch_bounds__(WG) void k_hist(const Seg *__restrict__ segs, const
         const uint32_t i = (uint32_t)j * WG + threadIdx.x;
         r[j] = in[b + (i < n ? i : n - 1)];
     }
+    // records arrive in emission order, so a wave's lanes often share one
+    // digit: then one atomic adds them all (otherwise 64 atomics on one
+    // address would serialize)
 #pragma unroll
-    for (int j = 0; j < CHUNK / WG; j++)
-        if ((uint32_t)j * WG + threadIdx.x < n) atomicAdd(&h[(rec_idx(r[j]) >> sg.shift) & mask], 1u);
+    for (int j = 0; j < CHUNK / WG; j++) {
+        const bool v = (uint32_t)j * WG + threadIdx.x < n;
+        const uint32_t d = (rec_idx(r[j]) >> sg.shift) & mask;
+        const uint64_t act = ballot(v);
+        const uint32_t d0 = readlane(d, act ? ctz64(act) : 0u);
+        if (act && ballot(v && d == d0) == act) {
+            if (lane_id() == ctz64(act)) atomicAdd(&h[d0], (uint32_t)__builtin_popcountll(act));
+        } else if (v) {
+            atomicAdd(&h[d], 1u);
+        }
+    }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < (1u << sg.dbits); d += WG) hist[sg.hbase + (uint64_t)d * sg.nchunks + ch.c] = h[d];
+    const uint32_t nd = 1u << sg.dbits;
+    for (uint32_t d = threadIdx.x; d < nd; d += WG) hist[sg.hbase + (uint64_t)ch.c * nd + d] = h[d];
+}
+
+// Per segment: each digit's count in every chunk becomes the output
+// position of that chunk's first record of the digit (digit bases in digit
+// order, chunks in order within a digit); starts[sbase + d] = first output
+// position of digit d.  One workgroup per segment; each thread walks the
+// chunks for its digits (reads coalesced across digits).
+__global__ __launch_bounds__(WG) void k_offsets(const Seg *__restrict__ segs, uint32_t nsegs,
+                                                 unsigned long long *__restrict__ hist,
+                                                 unsigned long long *__restrict__ starts) {
+    __shared__ unsigned long long tot[RADIX];
+    const uint32_t s = blockIdx.x;
+    if (s >= nsegs) return;
+    const Seg sg = segs[s];
+    const uint32_t nd = 1u << sg.dbits;
+    unsigned long long *H = hist + sg.hbase;
+    for (uint32_t d = threadIdx.x; d < nd; d += WG) {
+        unsigned long long t = 0;
+#pragma unroll 8
+        for (uint32_t c = 0; c < sg.nchunks; c++) t += H[(uint64_t)c * nd + d];
+        tot[d] = t;
+    }
+    __syncthreads();
+    {
+        // exclusive scan of the digit totals: each thread takes nd / WG
+        // consecutive digits, then a wave and a cross-wave scan
+        __shared__ unsigned long long wsum[WG / 64];
+        const uint32_t per = (nd + WG - 1) / WG;
+        const uint32_t d0 = threadIdx.x * per;
+        unsigned long long loc = 0;
+        for (uint32_t k = 0; k < per; k++)
+            if (d0 + k < nd) loc += tot[d0 + k];
+        unsigned long long inc = loc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(inc, (unsigned)o);
+            if ((int)lane_id() >= o) inc += y;
+        }
+        if (lane_id() == 63) wsum[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        unsigned long long run = sg.obase + inc - loc;
+        for (uint32_t w = 0; w < (threadIdx.x >> 6); w++) run += wsum[w];
+        for (uint32_t k = 0; k < per; k++) {
+            if (d0 + k < nd) {
+                const unsigned long long t = tot[d0 + k];
+                tot[d0 + k] = run;
+                run += t;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nd; d += WG) {
+        unsigned long long run = tot[d];
+        starts[(uint64_t)sg.sbase + d] = run;
+#pragma unroll 8
+        for (uint32_t c = 0; c < sg.nchunks; c++) {
+            const unsigned long long x = H[(uint64_t)c * nd + d];
+            H[(uint64_t)c * nd + d] = run;
+            run += x;
+        }
+    }
 }
 
 __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, const Chunk *__restrict__ chunks,
@@ -1501,7 +1574,7 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
     const uint32_t nd = 1u << sg.dbits;
     for (uint32_t d = threadIdx.x; d < nd; d += WG) {
         cur[d] = 0;
-        base[d] = offs[sg.hbase + (uint64_t)d * sg.nchunks + ch.c];
+        base[d] = offs[sg.hbase + (uint64_t)ch.c * nd + d];
     }
     __syncthreads();
     const uint64_t b = sg.start + (uint64_t)ch.c * CHUNK;
@@ -1515,11 +1588,20 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
     }
 #pragma unroll
     for (int j = 0; j < CHUNK / WG; j++) {
-        if ((uint32_t)j * WG + threadIdx.x < n) {
-            const uint32_t d = (rec_idx(r[j]) >> sg.shift) & mask;
-            const uint32_t o = atomicAdd(&cur[d], 1u);
-            if (base[d] + o < cap) out[base[d] + o] = r[j];
+        const bool v = (uint32_t)j * WG + threadIdx.x < n;
+        const uint32_t d = (rec_idx(r[j]) >> sg.shift) & mask;
+        const uint64_t act = ballot(v);
+        const uint32_t d0 = readlane(d, act ? ctz64(act) : 0u);
+        uint32_t o = 0;
+        if (act && ballot(v && d == d0) == act) {
+            // one reservation for the whole wave (same digit everywhere)
+            uint32_t b0 = 0;
+            if (lane_id() == ctz64(act)) b0 = atomicAdd(&cur[d0], (uint32_t)__builtin_popcountll(act));
+            o = readlane(b0, ctz64(act)) + mbcnt(act);
+        } else if (v) {
+            o = atomicAdd(&cur[d], 1u);
         }
+        if (v && base[d] + o < cap) out[base[d] + o] = r[j];
     }
 }
 
@@ -1795,6 +1877,11 @@ hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks
                           const unsigned long long *offs, unsigned long long *out, unsigned long long cap,
                           hipStream_t s) {
     return launch(k_scatter, dim3(nchunks), dim3(WG), s, segs, chunks, in, offs, out, cap);
+}
+
+hipError_t launch_offsets(const Seg *segs, uint32_t nsegs, unsigned long long *hist, unsigned long long *starts,
+                          hipStream_t s) {
+    return launch(k_offsets, dim3(nsegs), dim3(WG), s, segs, nsegs, hist, starts);
 }
 
 hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs, unsigned long long *starts,

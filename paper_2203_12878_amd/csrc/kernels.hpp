@@ -19,7 +19,8 @@ constexpr uint32_t FILTER_BITS = 18; // tiles spanning at most 2^18 index values
 struct Seg {
     uint64_t start;       // first record in the input buffer
     uint64_t len;
-    uint64_t hbase;       // histogram base: digit-major, chunk-minor
+    uint64_t obase;       // first record of the segment in the output buffer
+    uint64_t hbase;       // histogram base: chunk-major (chunk c, digit d at hbase + c * 2^dbits + d)
     uint32_t nchunks;
     uint32_t proto;
     uint32_t phase;       // local phase
@@ -79,6 +80,8 @@ hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, c
                        unsigned long long *hist, hipStream_t s);
 
 hipError_t launch_scan_u64(unsigned long long *data, uint64_t n, unsigned long long *tmp, hipStream_t s);
+hipError_t launch_offsets(const Seg *segs, uint32_t nsegs, unsigned long long *hist, unsigned long long *starts,
+                          hipStream_t s);
 uint64_t scan_tmp_words(uint64_t n);
 
 hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
