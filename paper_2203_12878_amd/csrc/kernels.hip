@@ -915,11 +915,12 @@ DEV unsigned long long block_ext64(unsigned long long v, uint32_t *red) {
 //          Definition 1 needs nothing else: the cell races iff a second tid
 //          and a writer exist, and the witness is (least tid, least other
 //          tid if the least tid writes, else least writer).
-//  filter  span <= 2^FILTER_BITS: a seen / repeated bitmap pair removes
-//          every cell touched by a single record (one access cannot race);
-//          the records left are sorted and scanned.
-//  sort    otherwise, or when more than FILTER_CAP records survive the
-//          filter: the whole group is sorted and scanned.
+//  filter  otherwise: a seen / repeated bitmap pair (indexed by the cell's
+//          offset when the span fits 2^FILTER_BITS bits, else by a hash of
+//          the cell) removes every cell touched by a single record (one
+//          access cannot race); the records left are sorted and scanned.
+//  sort    when more than FILTER_CAP records survive the filter: the whole
+//          group is sorted and scanned.
 // Tiles run 512-thread workgroups: at most 16 records per thread stay in
 // registers, and the two workgroups the LDS admits per CU give 4 waves per
 // SIMD.
@@ -933,6 +934,14 @@ static_assert(TILE % TWG == 0 && TILE / TWG <= 16, "tile records per thread");
 static_assert(FUSED_PACK % WG == 0, "fused group size");
 constexpr uint32_t RED_WORDS = 5 * (TWG / 64) + 1;       // scan slots of the widest workgroup, then
 constexpr uint32_t RED_CAND = RED_WORDS - 1;             // the filter's candidate counter
+
+// Bit of a cell in the filter bitmaps: its offset from the least cell when
+// the span fits the bitmap, else a multiplicative hash of the cell.  Equal
+// cells always share a bit, so no cell touched twice can be missed; a hash
+// collision only lets a single record through to the exact sort.
+DEV uint32_t filter_bit(unsigned long long cell, unsigned long long lo, bool hashed, uint32_t bits) {
+    return hashed ? (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64 - bits)) : (uint32_t)(cell - lo);
+}
 
 template <int E, int NT>
 DEV void sort_e(unsigned long long *a, uint32_t n) {
@@ -1018,8 +1027,9 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
     // one sort call site for both the filter's survivors and the whole group
     uint32_t n_sort = (uint32_t)NT * E, cnt_sort = cnt;
     bool filtered = false;
-    if (span <= (1ull << FILTER_BITS)) {
-        const uint32_t nw = (uint32_t)((span + 31) >> 5);
+    {
+        const bool hashed = span > (1ull << FILTER_BITS);
+        const uint32_t nw = hashed ? FILTER_WORDS : (uint32_t)((span + 31) >> 5);
         uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
         for (uint32_t k = threadIdx.x; k < nw; k += NT) {
             seen[k] = 0;
@@ -1030,7 +1040,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                const uint32_t b = (uint32_t)((u[j] >> ish) - lo), bit = 1u << (b & 31);
+                const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS), bit = 1u << (b & 31);
                 if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
             }
         }
@@ -1039,7 +1049,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         // (the seen bitmap is no longer read)
 #pragma unroll
         for (int j = 0; j < E; j++) {
-            const uint32_t b = (uint32_t)((u[j] >> ish) - lo);
+            const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
             const bool keep = (uint32_t)j * NT + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
             const uint64_t m = ballot(keep);
             if (m) {
@@ -1165,8 +1175,9 @@ DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t
     }
 
     uint32_t n_sort = npow, cnt_sort = cnt;
-    if (span <= (1ull << LDS_FILTER_BITS)) {
-        const uint32_t nw = (uint32_t)((span + 31) >> 5);
+    {
+        const bool hashed = span > (1ull << LDS_FILTER_BITS);
+        const uint32_t nw = hashed ? LDS_FWORDS : (uint32_t)((span + 31) >> 5);
         uint32_t *seen = sw, *rep = sw + LDS_FWORDS;
         unsigned long long *surv = reinterpret_cast<unsigned long long *>(seen);
         for (uint32_t k = threadIdx.x; k < nw; k += NT) {
@@ -1176,7 +1187,7 @@ DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t
         if (threadIdx.x == 0) red[RED_CAND] = 0;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-            const uint32_t b = (uint32_t)((a[ph(i)] >> ish) - lo), bit = 1u << (b & 31);
+            const uint32_t b = filter_bit(a[ph(i)] >> ish, lo, hashed, LDS_FILTER_BITS), bit = 1u << (b & 31);
             if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
         }
         __syncthreads();
@@ -1187,7 +1198,7 @@ DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t
             bool keep = false;
             if (i < cnt) {
                 r = a[ph(i)];
-                const uint32_t b = (uint32_t)((r >> ish) - lo);
+                const uint32_t b = filter_bit(r >> ish, lo, hashed, LDS_FILTER_BITS);
                 keep = ((rep[b >> 5] >> (b & 31)) & 1u) != 0;
             }
             const uint64_t m = ballot(keep);
