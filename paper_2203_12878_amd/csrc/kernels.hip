@@ -907,6 +907,28 @@ DEV unsigned long long block_ext64(unsigned long long v, uint32_t *red) {
     return r;
 }
 
+// Workgroup min and max of a u64 in one reduction (red[0 .. 4 * waves)).
+DEV void block_minmax64(unsigned long long &lo, unsigned long long &hi, uint32_t *red) {
+    lo = wave_min64(lo);
+    hi = wave_max64(hi);
+    __syncthreads();
+    if (lane_id() == 0) {
+        const uint32_t w = threadIdx.x >> 6;
+        red[4 * w] = (uint32_t)lo;
+        red[4 * w + 1] = (uint32_t)(lo >> 32);
+        red[4 * w + 2] = (uint32_t)hi;
+        red[4 * w + 3] = (uint32_t)(hi >> 32);
+    }
+    __syncthreads();
+    for (uint32_t w = 0; w < (blockDim.x >> 6); w++) {
+        const unsigned long long l = ((unsigned long long)red[4 * w + 1] << 32) | red[4 * w];
+        const unsigned long long h = ((unsigned long long)red[4 * w + 3] << 32) | red[4 * w + 2];
+        lo = l < lo ? l : lo;
+        hi = h > hi ? h : hi;
+    }
+    __syncthreads();
+}
+
 // A group of records (one phase, or consecutive phases in the packed
 // layout) is decided by one of three methods, chosen from the span of its
 // cells (cell = record >> (tb + 1): the index, or phase and index):
@@ -934,6 +956,79 @@ static_assert(TILE % TWG == 0 && TILE / TWG <= 16, "tile records per thread");
 static_assert(FUSED_PACK % WG == 0, "fused group size");
 constexpr uint32_t RED_WORDS = 5 * (TWG / 64) + 1;       // scan slots of the widest workgroup, then
 constexpr uint32_t RED_CAND = RED_WORDS - 1;             // the filter's candidate counter
+
+// Few survivors of the filter: instead of sorting them, aggregate them per
+// cell in an LDS hash table (open addressing on the 64-bit cell, linear
+// probing; at most HT_MAX records in HT_SLOTS slots, so probing ends) with
+// the table method's three minima per cell, then take the least racy
+// cell.  mem: HT_BYTES of LDS not overlapping the survivors.
+constexpr uint32_t HT_BITS = 10, HT_SLOTS = 1u << HT_BITS, HT_MAX = 512;
+constexpr uint32_t HT_BYTES = HT_SLOTS * (8 + 3 * 4);
+constexpr uint32_t RED_PAIR = 36;   // red[] words publishing the witness pair
+template <int NT>
+DEV bool hash_decide(const unsigned long long *surv, bool padded, uint32_t nc, uint32_t tb, void *mem, uint32_t *red,
+                     unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+    static_assert(HT_MAX <= 2 * NT, "two survivors per thread at most");
+    const uint32_t ish = tb + 1;
+    const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
+    unsigned long long *hk = reinterpret_cast<unsigned long long *>(mem);
+    uint32_t *t0 = reinterpret_cast<uint32_t *>(hk + HT_SLOTS), *w0 = t0 + HT_SLOTS, *t1 = w0 + HT_SLOTS;
+    for (uint32_t k = threadIdx.x; k < HT_SLOTS; k += NT) {
+        hk[k] = ~0ull;
+        t0[k] = NONE32;
+        w0[k] = NONE32;
+        t1[k] = NONE32;
+    }
+    __syncthreads();
+    uint32_t slot[2] = {NONE32, NONE32};
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const uint32_t i = threadIdx.x + (uint32_t)q * NT;
+        if (i < nc) {
+            const unsigned long long r = padded ? surv[ph(i)] : surv[i];
+            const unsigned long long c = r >> ish;
+            const uint32_t tid = (uint32_t)(r >> 1) & tmask;
+            uint32_t h = (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> (64 - HT_BITS));
+            for (;;) {
+                const unsigned long long old = atomicCAS(&hk[h], ~0ull, c);
+                if (old == ~0ull || old == c) break;
+                h = (h + 1) & (HT_SLOTS - 1);
+            }
+            atomicMin(&t0[h], tid);
+            if (r & 1ull) atomicMin(&w0[h], tid);
+            slot[q] = h;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const uint32_t i = threadIdx.x + (uint32_t)q * NT;
+        if (i < nc) {
+            const unsigned long long r = padded ? surv[ph(i)] : surv[i];
+            const uint32_t tid = (uint32_t)(r >> 1) & tmask;
+            if (tid != t0[slot[q]]) atomicMin(&t1[slot[q]], tid);
+        }
+    }
+    __syncthreads();
+    unsigned long long best = ~0ull;
+    for (uint32_t k = threadIdx.x; k < HT_SLOTS; k += NT)
+        if (hk[k] != ~0ull && t1[k] != NONE32 && w0[k] != NONE32 && hk[k] < best) best = hk[k];
+    unsigned long long none = 0;
+    block_minmax64(best, none, red);
+    if (best == ~0ull) return false;
+    for (uint32_t k = threadIdx.x; k < HT_SLOTS; k += NT) {
+        if (hk[k] == best) {   // the cell's one slot
+            red[RED_PAIR] = t0[k];
+            red[RED_PAIR + 1] = w0[k] == t0[k] ? t1[k] : w0[k];
+        }
+    }
+    __syncthreads();
+    key = best;
+    i1 = red[RED_PAIR];
+    i2 = red[RED_PAIR + 1];
+    __syncthreads();
+    return true;
+}
 
 // Bit of a cell in the filter bitmaps: its offset from the least cell when
 // the span fits the bitmap, else a multiplicative hash of the cell.  Equal
@@ -981,8 +1076,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         lo = x < lo ? x : lo;
         hi = x > hi ? x : hi;
     }
-    lo = block_ext64<false>(lo, red);
-    hi = block_ext64<true>(hi, red);
+    block_minmax64(lo, hi, red);
     const unsigned long long span = hi - lo + 1;   // cells are below 2^63
 
     if (span <= TBL_CELLS) {
@@ -1062,8 +1156,9 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         }
         __syncthreads();
         const uint32_t nc = red[RED_CAND];
+        if (nc == 0) return false;
+        if (nc <= HT_MAX) return hash_decide<NT>(a, true, nc, tb, rep, red, key, i1, i2);
         if (nc <= FILTER_CAP) {
-            if (nc == 0) return false;
             uint32_t np = NT;
             while (np < nc) np <<= 1;
             for (uint32_t k = nc + threadIdx.x; k < np; k += NT) a[ph(k)] = ~0ull;
@@ -1135,8 +1230,7 @@ DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t
         lo = x < lo ? x : lo;
         hi = x > hi ? x : hi;
     }
-    lo = block_ext64<false>(lo, red);
-    hi = block_ext64<true>(hi, red);
+    block_minmax64(lo, hi, red);
     const unsigned long long span = hi - lo + 1;   // cells are below 2^63
 
     if (span <= LDS_TBL_CELLS) {
@@ -1213,6 +1307,7 @@ DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t
         __syncthreads();
         const uint32_t nc = red[RED_CAND];
         if (nc == 0) return false;
+        if (nc <= HT_MAX) return hash_decide<NT>(surv, false, nc, tb, a, red, key, i1, i2);
         if (nc <= LDS_FCAP) {
             uint32_t np = NT;
             while (np < nc) np <<= 1;
