@@ -57,12 +57,18 @@ enum : uint32_t {
 // each lane then runs its short chain.  Layout (words, from cal_off):
 //   nacc nuni
 //   nuni x { len <postfix X_* code over loop variables> }
-//   nacc x { mode nops { opw arg } * nops }
+//   nacc x { mode form c0 m0k m0 a us pk pa nops { opw arg } * nops }
 // opw = C_* | (C_UNI if arg is a uniform slot, else arg is the immediate).
+// form 1: the chain is ((tid + c0) m0-op m0) * a + U[us] then pk-op pa, with
+// op kinds CAL_K_NONE / CAL_K_AND / CAL_K_MOD, us NONE32 when there is no
+// uniform term (the same operations as the chain, in the same order);
+// form 0: only the chain applies.
 enum : uint32_t {
     C_ADD = 1, C_MUL, C_MONUS, C_RMONUS, C_DIV, C_MOD, C_SHL, C_SHR, C_MIN, C_MAX, C_AND,
     C_UNI = 0x100,
 };
+constexpr uint32_t CAL_K_NONE = 0, CAL_K_AND = 1, CAL_K_MOD = 2;
+constexpr uint32_t CAL_HDR = 10;     // words before an access's chain ops
 constexpr uint32_t CAL_MAXU = 32;    // uniform slots of one leaf (a chunk then stages >= 64 iterations)
 constexpr uint32_t CAL_MAXOPS = 16;  // chain operations of one access
 

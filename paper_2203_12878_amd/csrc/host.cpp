@@ -921,9 +921,22 @@ struct Planner {
             }
         }
         for (size_t j = 0; j < accs.size(); j++) {
+            // the fixed form: [ADD c0] [AND|MOD m0] [MUL a] [ADD uniform] [AND|MOD pa]
+            // form c0 m0k m0 a us pk pa (mode before, nops after: CAL_HDR words in all)
+            uint32_t hdr[CAL_HDR - 2] = {0, 0, CAL_K_NONE, 0, 1, NONE32, CAL_K_NONE, 0};
+            size_t q = 0;
+            const auto &e = enc[j];
+            auto kind = [](uint32_t op) { return op == C_AND ? CAL_K_AND : op == C_MOD ? CAL_K_MOD : CAL_K_NONE; };
+            if (q < e.size() && e[q].first == C_ADD) { hdr[1] = e[q].second; q++; }
+            if (q < e.size() && (e[q].first == C_AND || e[q].first == C_MOD)) { hdr[2] = kind(e[q].first); hdr[3] = e[q].second; q++; }
+            if (q < e.size() && e[q].first == C_MUL) { hdr[4] = e[q].second; q++; }
+            if (q < e.size() && e[q].first == (C_ADD | C_UNI)) { hdr[5] = e[q].second; q++; }
+            if (q < e.size() && (e[q].first == C_AND || e[q].first == C_MOD)) { hdr[6] = kind(e[q].first); hdr[7] = e[q].second; q++; }
+            hdr[0] = q == e.size() ? 1u : 0u;
             c.push_back(ir.s[accs[j]].mode);
-            c.push_back((uint32_t)enc[j].size());
-            for (auto &o : enc[j]) { c.push_back(o.first); c.push_back(o.second); }
+            for (uint32_t w : hdr) c.push_back(w);
+            c.push_back((uint32_t)e.size());
+            for (auto &o : e) { c.push_back(o.first); c.push_back(o.second); }
         }
         return at;
     }

@@ -461,6 +461,24 @@ DEV uint32_t cal_chain(const uint32_t *__restrict__ ap, uint32_t nops, uint32_t 
     return v;
 }
 
+// Index of one compiled access (block at ap) for tid: the fixed form with
+// its parameters read once, else the chain.
+DEV uint32_t cal_index(const uint32_t *__restrict__ ap, uint32_t tid, const uint32_t *U, uint32_t ustride) {
+    if (rfl(ap[1]) == 1u) {
+        const uint32_t c0 = rfl(ap[2]), m0k = rfl(ap[3]), m0 = rfl(ap[4]), a = rfl(ap[5]), us = rfl(ap[6]);
+        const uint32_t pk = rfl(ap[7]), pa = rfl(ap[8]);
+        uint32_t v = tid + c0;
+        if (m0k == CAL_K_AND) v &= m0;
+        else if (m0k == CAL_K_MOD) v = m0 ? v % m0 : v;
+        v *= a;
+        if (us != NONE32) v += rfl(U[us * ustride]);
+        if (pk == CAL_K_AND) v &= pa;
+        else if (pk == CAL_K_MOD) v = pa ? v % pa : v;
+        return v;
+    }
+    return cal_chain(ap + CAL_HDR, rfl(ap[CAL_HDR - 1]), tid, U, ustride);
+}
+
 struct CalLds {
     uint32_t u[CAL_U];
     uint32_t ph[CAL_CH];
@@ -489,8 +507,6 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
     const uint32_t chmax = (CAL_U / nu) / 64 * 64 < CAL_CH ? (CAL_U / nu) / 64 * 64 : CAL_CH;   // >= 64
     const uint32_t tid = it.tid0 + threadIdx.x;
     const bool act0 = tid < pd.n;
-    EmitSink sink{nullptr, 0, recs, 0, tid};
-    sink.cap = cap;
     for (uint64_t fc = it.f0; fc < it.f1; fc += chmax) {
         const uint32_t ch = (uint32_t)(it.f1 - fc < chmax ? it.f1 - fc : chmax);
         const uint32_t chp = (ch + 63) & ~63u;
@@ -518,14 +534,24 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
             const unsigned long long b = lds_base[pi];
             const uint32_t lim = rfl(L.lim[i]);
             if (b == ~0ull || it.tid0 >= lim) continue;
+            // a compiled leaf has no branches: the wave's active lanes are
+            // the same for every access of the iteration, so one
+            // reservation covers all of them (access j, lane l at
+            // r0 + j * na + rank of l)
             const bool act = act0 && tid < lim;
-            sink.cur = &lds_cur[pi];
-            sink.base = b;
+            const uint64_t m = ballot(act);
+            if (m == 0) continue;
+            const uint32_t na = (uint32_t)__builtin_popcountll(m);
+            uint32_t r0 = 0;
+            if (lane_id() == 0) r0 = atomicAdd(&lds_cur[pi], na * nacc);
+            const unsigned long long p0 = b + readlane(r0, 0) + mbcnt(m);
             const uint32_t *ap = acc0;
             for (uint32_t j = 0; j < nacc; j++) {
-                const uint32_t mode = rfl(ap[0]), nops = rfl(ap[1]);
-                sink.acc(act, cal_chain(ap + 2, nops, tid, L.u + i, chp), mode);
-                ap += 2 + 2 * nops;
+                const uint32_t mode = rfl(ap[0]);
+                const uint32_t v = cal_index(ap, tid, L.u + i, chp);
+                const unsigned long long pos = p0 + (unsigned long long)j * na;
+                if (act && pos < cap) recs[pos] = ((unsigned long long)v << 32) | ((unsigned long long)tid << 1) | mode;
+                ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
             }
         }
         __syncthreads();
@@ -1464,12 +1490,22 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                                 for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
                                     const uint32_t tid = t0 + threadIdx.x;
                                     const bool act = tid < pd.n && tid < lim;
-                                    FusedSink sink{lds_rec, &lds_n, pre, ish, tid};
+                                    // one reservation per wave for all accesses (no branches)
+                                    const uint64_t m = ballot(act);
+                                    if (m == 0) continue;
+                                    const uint32_t na = (uint32_t)__builtin_popcountll(m);
+                                    uint32_t r0 = 0;
+                                    if (lane_id() == 0) r0 = atomicAdd(&lds_n, na * nacc);
+                                    const uint32_t p0 = readlane(r0, 0) + mbcnt(m);
                                     const uint32_t *ap = acc0;
                                     for (uint32_t j = 0; j < nacc; j++) {
-                                        const uint32_t mode = rfl(ap[0]), nops = rfl(ap[1]);
-                                        sink.acc(act, cal_chain(ap + 2, nops, tid, U, cs), mode);
-                                        ap += 2 + 2 * nops;
+                                        const uint32_t mode = rfl(ap[0]);
+                                        const uint32_t v = cal_index(ap, tid, U, cs);
+                                        const uint32_t pos = p0 + j * na;
+                                        if (act && pos < (uint32_t)TILE)
+                                            lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
+                                                               ((unsigned long long)tid << 1) | mode;
+                                        ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
                                     }
                                 }
                             }
