@@ -29,6 +29,8 @@
 #include <chrono>
 #include <functional>
 #include <thread>
+#include <tuple>
+#include <initializer_list>
 #include <vector>
 
 #include "../../include/drf.h"
@@ -49,6 +51,9 @@ struct drf_ctx {
     size_t sizeB = 0;
     hipEvent_t done = nullptr;
     hipEvent_t counted = nullptr;
+    hipEvent_t parted = nullptr;        // a partition level's bucket starts are on the host
+    void *h_starts = nullptr;           // pinned host copy of those starts
+    size_t h_starts_cap = 0;
     bool done_valid = false;
     uint32_t cus = 256;
     drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 16, 1u << 16};
@@ -250,6 +255,22 @@ struct Call {
         uint32_t *q = (uint32_t *)p;
         const uint64_t n = bytes / 4;
         dev([=](hipStream_t s) { return launch_fill_u32(q, word, n, s); });
+    }
+    // several fills (pointer, word, bytes) as one launch
+    void fill_many(std::initializer_list<std::tuple<void *, uint32_t, size_t>> fs) {
+        FillList L{};
+        for (const auto &f : fs) {
+            if (L.count == (uint32_t)FILL_MAX) {
+                const FillList M = L;
+                dev([=](hipStream_t s) { return launch_fill_multi(M, s); });
+                L = FillList{};
+            }
+            L.p[L.count] = (uint32_t *)std::get<0>(f);
+            L.v[L.count] = std::get<1>(f);
+            L.n[L.count] = std::get<2>(f) / 4;
+            L.count++;
+        }
+        if (L.count) dev([=](hipStream_t s) { return launch_fill_multi(L, s); });
     }
     // upload host data; a recorded call gives every upload its own memory
     template <class T>
@@ -655,18 +676,39 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             Prof pr(ctx, st, K_HIST, op, op * 8);
             C.dev([=](hipStream_t s) { return launch_hist(dsegs, dch, nch, cin, hist, s); });
         }
+        // The bucket starts are only read by the host: the offsets kernel
+        // writes them straight into pinned host memory, and the host builds
+        // the next tiles while the scatter runs.  A recorded call writes them
+        // to device memory and copies them back (its replays must not write
+        // host memory that may since have been released).
+        if (nstarts * 8 > ctx->h_starts_cap) {
+            if (ctx->h_starts) hipck(hipHostFree(ctx->h_starts));
+            ctx->h_starts = nullptr;
+            ctx->h_starts_cap = 0;
+            const size_t want = std::max<size_t>(nstarts * 8, 8u << 20);
+            if (hipHostMalloc(&ctx->h_starts, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+                ctx->h_starts = nullptr;
+                (void)hipGetLastError();
+                throw Fail{DRF_E_NOMEM};
+            }
+            ctx->h_starts_cap = want;
+        }
+        const uint64_t *starts = (const uint64_t *)ctx->h_starts;
+        unsigned long long *wstarts = dstarts;
+        if (!C.rec) hipck(hipHostGetDevicePointer((void **)&wstarts, ctx->h_starts, 0));
         {
             // counts in, output positions out (read twice, written once)
             Prof pr(ctx, st, K_SCAN, 0, hb * 24);
-            C.dev([=](hipStream_t s) { return launch_offsets(dsegs, nsg, hist, dstarts, s); });
+            C.dev([=](hipStream_t s) { return launch_offsets(dsegs, nsg, hist, wstarts, s); });
         }
+        if (C.rec) hipck(hipMemcpyAsync(ctx->h_starts, dstarts, nstarts * 8, hipMemcpyDeviceToHost, st));
+        if (!ctx->parted) hipck(hipEventCreateWithFlags(&ctx->parted, hipEventDisableTiming));
+        hipck(hipEventRecord(ctx->parted, st));
         {
             Prof pr(ctx, st, K_SCATTER, op, op * 16);
             C.dev([=](hipStream_t s) { return launch_scatter(dsegs, dch, nch, cin, hist, cout, recs, s); });
         }
-        std::vector<uint64_t> starts(nstarts);
-        hipck(hipMemcpyAsync(starts.data(), dstarts, starts.size() * 8, hipMemcpyDeviceToHost, st));
-        C.sync();
+        hipck(hipEventSynchronize(ctx->parted));
         C.tr.mark("level partitioned", segs.size());
 
         std::vector<Seg> next;
@@ -675,45 +717,49 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         for (size_t s2 = 0; s2 < segs.size(); s2++) {
             const Seg &sg = segs[s2];
             const uint32_t nd = 1u << sg.dbits;
+            const uint64_t *S = starts + sg.sbase;
+            const uint64_t send = out_start[s2] + sg.len;
+            auto end = [&](uint32_t x) { return x + 1 < nd ? S[x + 1] : send; };
             // consecutive small buckets of one segment are contiguous and
-            // hold disjoint index values: one tile takes several of them.
-            // When one bucket spans few enough index values for the tile
-            // kernel's singleton filter, a tile stays within that span.
-            Tile cur{0, 0, sg.proto, sg.phase, 0};
-            uint32_t cur_d0 = 0;
-            const bool span_cap = sg.shift < FILTER_BITS;
-            for (uint32_t d = 0; d < nd; d++) {
-                const uint64_t a0 = starts[sg.sbase + d];
-                const uint64_t e = (d + 1 < nd) ? starts[sg.sbase + d + 1] : out_start[s2] + sg.len;
-                const uint64_t len = e - a0;
-                if (len == 0) continue;
-                if (len <= (uint64_t)tile) {
-                    const bool in_span = !span_cap || ((uint64_t)(d - cur_d0 + 1) << sg.shift) <= (1ull << FILTER_BITS);
-                    if (cur.len && cur.start + cur.len == a0 && cur.len + len <= (uint64_t)tile && in_span) {
-                        cur.len += (uint32_t)len;
-                    } else {
-                        if (cur.len) tiles.push_back(cur);
-                        cur.start = a0;
-                        cur.len = (uint32_t)len;
-                        cur_d0 = d;
-                    }
+            // hold disjoint index values: one tile takes the longest run of
+            // them that fits.  When one bucket spans few enough index values
+            // for the tile kernel's singleton filter, a tile stays within
+            // that span.
+            const uint32_t span = sg.shift < FILTER_BITS ? 1u << (FILTER_BITS - sg.shift) : nd;
+            uint32_t d = 0;
+            while (d < nd) {
+                const uint64_t a0 = S[d], len = end(d) - a0;
+                if (len == 0) {
+                    d++;
                     continue;
                 }
-                if (cur.len) { tiles.push_back(cur); cur.len = 0; }
-                if (sg.shift == 0) {
-                    g2.push_back(Group{a0, len, sg.proto, sg.phase});
-                } else {
-                    Seg ns{};
-                    ns.start = a0;
-                    ns.len = len;
-                    ns.proto = sg.proto;
-                    ns.phase = sg.phase;
-                    ns.dbits = std::min<uint32_t>(digit_bits_for(len, dbits), sg.shift);
-                    ns.shift = sg.shift - ns.dbits;
-                    next.push_back(ns);
+                if (len > (uint64_t)tile) {
+                    if (sg.shift == 0) {
+                        g2.push_back(Group{a0, len, sg.proto, sg.phase});
+                    } else {
+                        Seg ns{};
+                        ns.start = a0;
+                        ns.len = len;
+                        ns.proto = sg.proto;
+                        ns.phase = sg.phase;
+                        ns.dbits = std::min<uint32_t>(digit_bits_for(len, dbits), sg.shift);
+                        ns.shift = sg.shift - ns.dbits;
+                        next.push_back(ns);
+                    }
+                    d++;
+                    continue;
                 }
+                // largest x in [d, d + span) with end(x) - a0 <= tile (ends are nondecreasing)
+                uint32_t lo = d, hi = std::min<uint32_t>(nd - 1, d + span - 1);
+                const uint64_t lim = a0 + tile;
+                while (lo < hi) {
+                    const uint32_t m = (lo + hi + 1) >> 1;
+                    if (end(m) <= lim) lo = m;
+                    else hi = m - 1;
+                }
+                tiles.push_back(Tile{a0, (uint32_t)(end(lo) - a0), sg.proto, sg.phase, 0});
+                d = lo + 1;
             }
-            if (cur.len) tiles.push_back(cur);
         }
         run_tiles(tiles, out);
         if (!g2.empty()) run_groups(g2, out);
@@ -766,14 +812,14 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             upload(C.keep, at<void>(A, C.o_fixed), C.fixed, st);
             upload(C.keep, at<void>(A, C.o_code), C.code, st);
         }
-        if (C.total_phases) C.fill32(phase_counts, 0, C.total_phases * sizeof(uint64_t));
-        C.fill32(ovf, 0, count * sizeof(uint32_t));
-        C.fill32(best, 0xFFFFFFFFu, count * sizeof(Best));
         uint32_t *item_cnt = at<uint32_t>(A, C.o_itemcnt);
         unsigned long long *nrec_dev = at<unsigned long long>(A, C.o_nrec);
         uint32_t *qhead = at<uint32_t>(A, C.o_qhead);
-        C.fill32(nrec_dev, 0, count * sizeof(uint64_t));
-        C.fill32(qhead, 0, 64 * sizeof(uint32_t));
+        C.fill_many({{phase_counts, 0u, C.total_phases * sizeof(uint64_t)},
+                     {ovf, 0u, count * sizeof(uint32_t)},
+                     {best, 0xFFFFFFFFu, count * sizeof(Best)},
+                     {nrec_dev, 0u, count * sizeof(uint64_t)},
+                     {qhead, 0u, 64 * sizeof(uint32_t)}});
         const uint32_t fgrid = ctx->cus * 2;
         const uint32_t small = small_events(ctx);
         int qslot = 0;
@@ -1058,6 +1104,8 @@ int drf_ctx_destroy(drf_ctx *ctx) {
     if (ctx->poolB) (void)hipFree(ctx->poolB);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->counted) (void)hipEventDestroy(ctx->counted);
+    if (ctx->parted) (void)hipEventDestroy(ctx->parted);
+    if (ctx->h_starts) (void)hipHostFree(ctx->h_starts);
     for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     delete ctx;

@@ -1905,6 +1905,18 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, uint64_t n) {
         p[i] = v;
 }
 
+// Block b fills part of the fill whose block range holds b.
+__global__ void k_fill_multi(FillList L) {
+    const uint32_t b = blockIdx.x;
+    uint32_t f = 0;
+    while (f + 1 < L.count && b >= L.b0[f + 1]) f++;
+    const uint64_t nb = (f + 1 < L.count ? L.b0[f + 1] : gridDim.x) - L.b0[f];
+    uint32_t *__restrict__ p = L.p[f];
+    const uint32_t v = L.v[f];
+    const uint64_t n = L.n[f];
+    for (uint64_t i = (uint64_t)(b - L.b0[f]) * 256 + threadIdx.x; i < n; i += nb * 256) p[i] = v;
+}
+
 __global__ void k_init_acc(SingleAcc *__restrict__ a, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = SingleAcc{NONE32, NONE32, 0u, NONE32};
@@ -2056,6 +2068,24 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint64_t blocks = (n + 255) / 256;
     return launch(k_fill_u32, dim3((uint32_t)(blocks < 4096 ? blocks : 4096)), dim3(256), s, p, v, n);
+}
+
+hipError_t launch_fill_multi(FillList L, hipStream_t s) {
+    // empty fills are dropped; each remaining one gets its own blocks
+    FillList M{};
+    uint32_t blocks = 0;
+    for (uint32_t i = 0; i < L.count && i < (uint32_t)FILL_MAX; i++) {
+        if (L.n[i] == 0) continue;
+        const uint32_t k = M.count++;
+        M.p[k] = L.p[i];
+        M.n[k] = L.n[i];
+        M.v[k] = L.v[i];
+        M.b0[k] = blocks;
+        const uint64_t nb = (L.n[i] + 255) / 256;
+        blocks += (uint32_t)(nb < 1024 ? nb : 1024);
+    }
+    if (M.count == 0) return hipSuccess;
+    return launch(k_fill_multi, dim3(blocks), dim3(256), s, M);
 }
 
 hipError_t launch_init_acc(SingleAcc *a, uint32_t n, hipStream_t s) {

@@ -99,6 +99,17 @@ hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned l
 
 hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
+
+// Up to FILL_MAX word fills in one launch (passed by value).
+constexpr int FILL_MAX = 8;
+struct FillList {
+    uint32_t *p[FILL_MAX];
+    uint64_t n[FILL_MAX];        // words
+    uint32_t v[FILL_MAX];
+    uint32_t b0[FILL_MAX];       // first block of each fill (set by the launcher)
+    uint32_t count;
+};
+hipError_t launch_fill_multi(FillList L, hipStream_t s);
 hipError_t launch_init_acc(SingleAcc *a, uint32_t n, hipStream_t s);
 
 // Final per-protocol result (same layout as drf_result of the C ABI).
