@@ -1564,10 +1564,19 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             if (npow <= (uint32_t)FUSED_PACK) {
                 f = decide_lds<WG>(lds_rec, cnt, npow, tb, lds_res, key, r1, r2);
             } else {
-                // one phase above FUSED_PACK events: sorted and scanned whole
-                for (uint32_t i = cnt + threadIdx.x; i < npow; i += WG) lds_rec[ph(i)] = ~0ull;
+                // one phase above FUSED_PACK events leaves no LDS scratch:
+                // its records move to registers (lanes past the end copy the
+                // last one) and the whole array becomes the scratch of the
+                // table / filter / sort decision
+                constexpr int FE = TILE / WG;
+                unsigned long long v[FE];
+#pragma unroll
+                for (int j = 0; j < FE; j++) {
+                    const uint32_t i = (uint32_t)j * WG + threadIdx.x;
+                    v[j] = lds_rec[ph(i < cnt ? i : cnt - 1)];
+                }
                 __syncthreads();
-                f = sort_scan<WG>(lds_rec, npow, cnt, tb, lds_res, key, r1, r2);
+                f = decide<FE, WG>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
             }
             if (f && !have) {
                 have = true;
