@@ -956,8 +956,9 @@ DEV void block_minmax64(unsigned long long &lo, unsigned long long &hi, uint32_t
 }
 
 // A group of records (one phase, or consecutive phases in the packed
-// layout) is decided by one of three methods, chosen from the span of its
-// cells (cell = record >> (tb + 1): the index, or phase and index):
+// layout; at most TILE, held in registers) is decided with the group's LDS
+// array as scratch, by a method chosen from the span of its cells (cell =
+// record >> (tb + 1): the index, or phase and index):
 //  table   span <= TBL_CELLS: per cell, the least tid, the least writing
 //          tid and the least tid other than the first, by LDS atomics.
 //          Definition 1 needs nothing else: the cell races iff a second tid
@@ -966,94 +967,109 @@ DEV void block_minmax64(unsigned long long &lo, unsigned long long &hi, uint32_t
 //  filter  otherwise: a seen / repeated bitmap pair (indexed by the cell's
 //          offset when the span fits 2^FILTER_BITS bits, else by a hash of
 //          the cell) removes every cell touched by a single record (one
-//          access cannot race); the records left are sorted and scanned.
-//  sort    when more than FILTER_CAP records survive the filter: the whole
-//          group is sorted and scanned.
+//          access cannot race).  When no cell repeats the group is race
+//          free; otherwise the records left are aggregated per cell as in
+//          the table method, in an LDS hash table.
+//  sort    when the survivors hold more distinct cells than the hash table
+//          takes: they are sorted and scanned.
 // Tiles run 512-thread workgroups: at most 16 records per thread stay in
 // registers, and the two workgroups the LDS admits per CU give 4 waves per
 // SIMD.
 constexpr int TWG = 512;
 constexpr uint32_t TBL_CELLS = (TILE_LDS * 2) / 3;       // three u32 per cell
 constexpr uint32_t FILTER_WORDS = 1u << (FILTER_BITS - 5);
-constexpr uint32_t FILTER_CAP = 3968;                    // ph() slots below the repeated bitmap
 static_assert(2 * FILTER_WORDS <= 2 * TILE_LDS, "filter bitmaps exceed the group LDS");
-static_assert(FILTER_CAP - 1 + (FILTER_CAP - 1) / 32 < FILTER_WORDS / 2, "filter output overlaps its bitmap");
 static_assert(TILE % TWG == 0 && TILE / TWG <= 16, "tile records per thread");
+static_assert(TILE / WG <= 32, "fused records per thread (one mask bit each)");
 static_assert(FUSED_PACK % WG == 0, "fused group size");
 constexpr uint32_t RED_WORDS = 5 * (TWG / 64) + 1;       // scan slots of the widest workgroup, then
-constexpr uint32_t RED_CAND = RED_WORDS - 1;             // the filter's candidate counter
+constexpr uint32_t RED_CAND = RED_WORDS - 1;             // the filter's repeat flag / hash cell counter
+constexpr uint32_t RED_PAIR = 36;                        // the witness pair (after the reductions)
+constexpr uint32_t RED_OVF = 38;                         // hash table overflow flag
+constexpr uint32_t RED_NC = 39;                          // survivor count
+// Up to SURV_CAP survivors of the filter are also kept compact in LDS,
+// below the repeated bitmap; the hash table then lies above them.
+constexpr uint32_t SURV_CAP = 1024;
+constexpr uint32_t SURV_WORDS = 2 * (SURV_CAP + SURV_CAP / 32);
+static_assert(SURV_WORDS <= FILTER_WORDS, "compact survivors overlap the repeated bitmap");
+static_assert((2 * TILE_LDS - SURV_WORDS) / 4 >= 2 * SURV_CAP, "no room for the table above the survivors");
+static_assert(RED_PAIR >= 4 * (TWG / 64) && RED_PAIR + 1 < RED_OVF && RED_NC < RED_CAND,
+              "reduction slots overlap");
 
-// Few survivors of the filter: instead of sorting them, aggregate them per
-// cell in an LDS hash table (open addressing on the 64-bit cell, linear
-// probing; at most HT_MAX records in HT_SLOTS slots, so probing ends) with
-// the table method's three minima per cell, then take the least racy
-// cell.  mem: HT_BYTES of LDS not overlapping the survivors.
-constexpr uint32_t HT_BITS = 10, HT_SLOTS = 1u << HT_BITS, HT_MAX = 512;
-constexpr uint32_t HT_BYTES = HT_SLOTS * (8 + 3 * 4);
-constexpr uint32_t RED_PAIR = 36;   // red[] words publishing the witness pair
-template <int NT>
-DEV bool hash_decide(const unsigned long long *surv, bool padded, uint32_t nc, uint32_t tb, void *mem, uint32_t *red,
-                     unsigned long long &key, uint32_t &i1, uint32_t &i2) {
-    static_assert(HT_MAX <= 2 * NT, "two survivors per thread at most");
-    const uint32_t ish = tb + 1;
-    const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
-    unsigned long long *hk = reinterpret_cast<unsigned long long *>(mem);
-    uint32_t *t0 = reinterpret_cast<uint32_t *>(hk + HT_SLOTS), *w0 = t0 + HT_SLOTS, *t1 = w0 + HT_SLOTS;
-    for (uint32_t k = threadIdx.x; k < HT_SLOTS; k += NT) {
-        hk[k] = ~0ull;
-        t0[k] = NONE32;
-        w0[k] = NONE32;
-        t1[k] = NONE32;
+// Exact decision of the filter's survivors by per-cell aggregation in an
+// LDS hash table at mem: open addressing on the cell's offset from lo (the
+// span is below 2^32), linear probing over 2^hb slots of (key, least tid,
+// least writing tid, least tid other than the first), the table sized for
+// twice the survivors.  Probing never takes more steps than there are
+// slots; more distinct cells than three quarters of the slots is an
+// overflow.  src(f) calls f(record) for each survivor this thread owns (the
+// same ones on every call).  Returns 1 (racy cell found), 0 (none) or -1
+// (overflow: the caller sorts instead).
+constexpr uint32_t HSLOTS_MAX = 4096;
+static_assert(HSLOTS_MAX * 16 <= TILE_LDS * 8, "hash table exceeds the group LDS");
+template <int NT, class Src>
+DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsigned long long lo, uint32_t *mem,
+                 uint32_t max_slots, uint32_t *red, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+    uint32_t hb = 8;
+    while ((1u << hb) < 2 * nc && (2u << hb) <= max_slots) hb++;
+    const uint32_t S = 1u << hb, cap = S - S / 4;
+    uint32_t *K = mem, *T0 = K + S, *W0 = T0 + S, *T1 = W0 + S;
+    for (uint32_t k = threadIdx.x; k < 4 * S; k += NT) K[k] = NONE32;
+    if (threadIdx.x == 0) {
+        red[RED_CAND] = 0;
+        red[RED_OVF] = 0;
     }
     __syncthreads();
-    uint32_t slot[2] = {NONE32, NONE32};
-#pragma unroll
-    for (int q = 0; q < 2; q++) {
-        const uint32_t i = threadIdx.x + (uint32_t)q * NT;
-        if (i < nc) {
-            const unsigned long long r = padded ? surv[ph(i)] : surv[i];
-            const unsigned long long c = r >> ish;
-            const uint32_t tid = (uint32_t)(r >> 1) & tmask;
-            uint32_t h = (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> (64 - HT_BITS));
-            for (;;) {
-                const unsigned long long old = atomicCAS(&hk[h], ~0ull, c);
-                if (old == ~0ull || old == c) break;
-                h = (h + 1) & (HT_SLOTS - 1);
+    bool ovf = false;
+    src([&](unsigned long long r) {
+        const uint32_t c = (uint32_t)((r >> ish) - lo);
+        const uint32_t tid = (uint32_t)(r >> 1) & tmask;
+        uint32_t h = (c * 0x9E3779B1u) >> (32 - hb);
+        bool placed = false;
+        for (uint32_t st = 0; st < S; st++) {
+            const uint32_t old = atomicCAS(&K[h], NONE32, c);
+            if (old == NONE32 || old == c) {
+                if (old == NONE32 && atomicAdd(&red[RED_CAND], 1u) >= cap) ovf = true;
+                placed = true;
+                break;
             }
-            atomicMin(&t0[h], tid);
-            if (r & 1ull) atomicMin(&w0[h], tid);
-            slot[q] = h;
+            h = (h + 1) & (S - 1);
+        }
+        if (placed) {
+            atomicMin(&T0[h], tid);
+            if (r & 1ull) atomicMin(&W0[h], tid);
+        } else {
+            ovf = true;
+        }
+    });
+    if (ovf) red[RED_OVF] = 1;
+    __syncthreads();
+    if (red[RED_OVF]) return -1;
+    src([&](unsigned long long r) {
+        const uint32_t c = (uint32_t)((r >> ish) - lo);
+        const uint32_t tid = (uint32_t)(r >> 1) & tmask;
+        uint32_t h = (c * 0x9E3779B1u) >> (32 - hb);
+        while (K[h] != c) h = (h + 1) & (S - 1);   // placed in the pass before
+        if (tid != T0[h]) atomicMin(&T1[h], tid);
+    });
+    __syncthreads();
+    uint32_t bc = NONE32;
+    for (uint32_t k = threadIdx.x; k < S; k += NT)
+        if (K[k] != NONE32 && T1[k] != NONE32 && W0[k] != NONE32 && K[k] < bc) bc = K[k];
+    bc = block_min(bc, red);
+    if (bc == NONE32) return 0;
+    for (uint32_t k = threadIdx.x; k < S; k += NT) {
+        if (K[k] == bc) {   // the cell's one slot
+            red[RED_PAIR] = T0[k];
+            red[RED_PAIR + 1] = W0[k] == T0[k] ? T1[k] : W0[k];
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; q++) {
-        const uint32_t i = threadIdx.x + (uint32_t)q * NT;
-        if (i < nc) {
-            const unsigned long long r = padded ? surv[ph(i)] : surv[i];
-            const uint32_t tid = (uint32_t)(r >> 1) & tmask;
-            if (tid != t0[slot[q]]) atomicMin(&t1[slot[q]], tid);
-        }
-    }
-    __syncthreads();
-    unsigned long long best = ~0ull;
-    for (uint32_t k = threadIdx.x; k < HT_SLOTS; k += NT)
-        if (hk[k] != ~0ull && t1[k] != NONE32 && w0[k] != NONE32 && hk[k] < best) best = hk[k];
-    unsigned long long none = 0;
-    block_minmax64(best, none, red);
-    if (best == ~0ull) return false;
-    for (uint32_t k = threadIdx.x; k < HT_SLOTS; k += NT) {
-        if (hk[k] == best) {   // the cell's one slot
-            red[RED_PAIR] = t0[k];
-            red[RED_PAIR + 1] = w0[k] == t0[k] ? t1[k] : w0[k];
-        }
-    }
-    __syncthreads();
-    key = best;
+    key = lo + bc;
     i1 = red[RED_PAIR];
     i2 = red[RED_PAIR + 1];
     __syncthreads();
-    return true;
+    return 1;
 }
 
 // Bit of a cell in the filter bitmaps: its offset from the least cell when
@@ -1144,9 +1160,10 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         return found;
     }
 
-    // one sort call site for both the filter's survivors and the whole group
-    uint32_t n_sort = (uint32_t)NT * E, cnt_sort = cnt;
-    bool filtered = false;
+    // filter: seen / repeated bitmaps, then the survivors: their mask per
+    // thread, and (up to SURV_CAP) a compact copy at a[ph(0..)], below the
+    // repeated bitmap (the seen bitmap is no longer read)
+    uint32_t keepm = 0, nc;
     {
         const bool hashed = span > (1ull << FILTER_BITS);
         const uint32_t nw = hashed ? FILTER_WORDS : (uint32_t)((span + 31) >> 5);
@@ -1155,55 +1172,84 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
             seen[k] = 0;
             rep[k] = 0;
         }
-        if (threadIdx.x == 0) red[RED_CAND] = 0;
+        if (threadIdx.x == 0) {
+            red[RED_CAND] = 0;
+            red[RED_NC] = 0;
+        }
         __syncthreads();
+        bool again = false;
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if ((uint32_t)j * NT + threadIdx.x < cnt) {
                 const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS), bit = 1u << (b & 31);
-                if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
+                if (atomicOr(&seen[b >> 5], bit) & bit) {
+                    atomicOr(&rep[b >> 5], bit);
+                    again = true;
+                }
             }
         }
+        if (again) red[RED_CAND] = 1;
         __syncthreads();
-        // survivors go to a[ph(0..)], which lies below the repeated bitmap
-        // (the seen bitmap is no longer read)
+        if (red[RED_CAND] == 0) return false;   // every cell touched once
 #pragma unroll
         for (int j = 0; j < E; j++) {
             const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
             const bool keep = (uint32_t)j * NT + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
             const uint64_t m = ballot(keep);
             if (m) {
+                keepm |= (keep ? 1u : 0u) << j;
+                uint32_t base = 0;
+                if (lane_id() == 0) base = atomicAdd(&red[RED_NC], (uint32_t)__builtin_popcountll(m));
+                base = __shfl(base, 0);
+                const uint32_t pos = base + mbcnt(m);
+                if (keep && pos < SURV_CAP) a[ph(pos)] = u[j];
+            }
+        }
+        __syncthreads();   // the bitmaps are read for the last time
+        nc = red[RED_NC];
+    }
+    const bool compact = nc <= SURV_CAP;
+    if (span <= 0xFFFFFFFFull) {
+        int r;
+        if (compact) {
+            // survivors spread over the threads, the table above them
+            auto src = [&](auto f) {
+                for (uint32_t i = threadIdx.x; i < nc; i += NT) f(a[ph(i)]);
+            };
+            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32 + SURV_WORDS, (2 * TILE_LDS - SURV_WORDS) / 4, red, key,
+                             i1, i2);
+        } else {
+            auto src = [&](auto f) {
+#pragma unroll
+                for (int j = 0; j < E; j++)
+                    if ((keepm >> j) & 1u) f(u[j]);
+            };
+            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32, HSLOTS_MAX, red, key, i1, i2);
+        }
+        if (r >= 0) return r == 1;
+        __syncthreads();   // every thread has seen the overflow
+    }
+    // sort the survivors (compacted to a[ph(0..nc))), padded to a power of two
+    if (!compact) {
+        if (threadIdx.x == 0) red[RED_CAND] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            const bool keep = (keepm >> j) & 1u;
+            const uint64_t m = ballot(keep);
+            if (m) {
                 uint32_t base = 0;
                 if (lane_id() == 0) base = atomicAdd(&red[RED_CAND], (uint32_t)__builtin_popcountll(m));
                 base = __shfl(base, 0);
-                const uint32_t pos = base + mbcnt(m);
-                if (keep && pos < FILTER_CAP) a[ph(pos)] = u[j];
+                if (keep) a[ph(base + mbcnt(m))] = u[j];
             }
         }
-        __syncthreads();
-        const uint32_t nc = red[RED_CAND];
-        if (nc == 0) return false;
-        if (nc <= HT_MAX) return hash_decide<NT>(a, true, nc, tb, rep, red, key, i1, i2);
-        if (nc <= FILTER_CAP) {
-            uint32_t np = NT;
-            while (np < nc) np <<= 1;
-            for (uint32_t k = nc + threadIdx.x; k < np; k += NT) a[ph(k)] = ~0ull;
-            n_sort = np;
-            cnt_sort = nc;
-            filtered = true;
-        }
-        // otherwise every thread has read nc and no bitmap is read again:
-        // the whole group is sorted
     }
-    if (!filtered) {
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            const uint32_t i = (uint32_t)j * NT + threadIdx.x;
-            a[ph(i)] = i < cnt ? u[j] : ~0ull;
-        }
-    }
+    uint32_t np = NT;
+    while (np < nc) np <<= 1;
+    for (uint32_t k = nc + threadIdx.x; k < np; k += NT) a[ph(k)] = ~0ull;
     __syncthreads();
-    return sort_scan<NT>(a, n_sort, cnt_sort, tb, red, key, i1, i2);
+    return sort_scan<NT>(a, np, nc, tb, red, key, i1, i2);
 }
 
 // =============================================================== fused path
@@ -1228,126 +1274,6 @@ struct FusedSink {
             lds[ph(pos)] = pre | ((unsigned long long)idx << ish) | ((unsigned long long)tid << 1) | mode;
     }
 };
-
-// Fused groups of at most FUSED_PACK events are decided with their records
-// left in LDS: they occupy a[0 .. ph(FUSED_PACK)) and the rest of the
-// TILE_LDS array is scratch for
-// the table (LDS_TBL_CELLS cells) or the filter bitmaps (spans up to
-// 2^LDS_FILTER_BITS).  The records are never overwritten before the last
-// method is chosen, so nothing has to stay in registers.
-constexpr uint32_t LDS_SOFF = FUSED_PACK + FUSED_PACK / 32;           // first scratch u64 (= ph(FUSED_PACK))
-constexpr uint32_t LDS_SWORDS = 2 * (TILE_LDS - LDS_SOFF);            // scratch u32 words
-constexpr uint32_t LDS_TBL_CELLS = LDS_SWORDS / 3;
-constexpr uint32_t LDS_FILTER_BITS = 17;
-constexpr uint32_t LDS_FWORDS = 1u << (LDS_FILTER_BITS - 5);
-constexpr uint32_t LDS_FCAP = LDS_FWORDS / 2;                         // survivors held in the seen bitmap's words
-static_assert(2 * LDS_FWORDS <= LDS_SWORDS, "fused filter bitmaps exceed the scratch");
-static_assert(LDS_FCAP <= FUSED_PACK, "fused filter survivors exceed a group");
-
-template <int NT>
-DEV bool decide_lds(unsigned long long *a, uint32_t cnt, uint32_t npow, uint32_t tb, uint32_t *red,
-                    unsigned long long &key, uint32_t &i1, uint32_t &i2) {
-    const uint32_t ish = tb + 1;
-    const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
-    uint32_t *sw = reinterpret_cast<uint32_t *>(a + LDS_SOFF);
-    unsigned long long lo = ~0ull, hi = 0;
-    for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-        const unsigned long long x = a[ph(i)] >> ish;
-        lo = x < lo ? x : lo;
-        hi = x > hi ? x : hi;
-    }
-    block_minmax64(lo, hi, red);
-    const unsigned long long span = hi - lo + 1;   // cells are below 2^63
-
-    if (span <= LDS_TBL_CELLS) {
-        const uint32_t sp = (uint32_t)span;
-        uint32_t *t0 = sw, *w0 = sw + sp, *t1 = sw + 2 * sp;
-        for (uint32_t k = threadIdx.x; k < 3 * sp; k += NT) sw[k] = NONE32;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-            const unsigned long long r = a[ph(i)];
-            const uint32_t b = (uint32_t)((r >> ish) - lo), tid = (uint32_t)(r >> 1) & tmask;
-            atomicMin(&t0[b], tid);
-            if (r & 1ull) atomicMin(&w0[b], tid);
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-            const unsigned long long r = a[ph(i)];
-            const uint32_t b = (uint32_t)((r >> ish) - lo), tid = (uint32_t)(r >> 1) & tmask;
-            if (tid != t0[b]) atomicMin(&t1[b], tid);
-        }
-        __syncthreads();
-        uint32_t first = NONE32;
-        for (uint32_t k = threadIdx.x; k < sp; k += NT) {
-            if (t1[k] != NONE32 && w0[k] != NONE32) { first = k; break; }
-        }
-        first = block_min(first, red);
-        bool found = false;
-        if (first != NONE32) {
-            found = true;
-            key = lo + first;
-            i1 = t0[first];
-            const uint32_t aw = w0[first];
-            i2 = aw == i1 ? t1[first] : aw;
-        }
-        __syncthreads();   // the table is read before the caller reuses the LDS
-        return found;
-    }
-
-    uint32_t n_sort = npow, cnt_sort = cnt;
-    {
-        const bool hashed = span > (1ull << LDS_FILTER_BITS);
-        const uint32_t nw = hashed ? LDS_FWORDS : (uint32_t)((span + 31) >> 5);
-        uint32_t *seen = sw, *rep = sw + LDS_FWORDS;
-        unsigned long long *surv = reinterpret_cast<unsigned long long *>(seen);
-        for (uint32_t k = threadIdx.x; k < nw; k += NT) {
-            seen[k] = 0;
-            rep[k] = 0;
-        }
-        if (threadIdx.x == 0) red[RED_CAND] = 0;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-            const uint32_t b = filter_bit(a[ph(i)] >> ish, lo, hashed, LDS_FILTER_BITS), bit = 1u << (b & 31);
-            if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&rep[b >> 5], bit);
-        }
-        __syncthreads();
-        // survivors go to the seen bitmap's words (no longer read)
-        for (uint32_t i0 = 0; i0 < cnt; i0 += NT) {
-            const uint32_t i = i0 + threadIdx.x;
-            unsigned long long r = 0;
-            bool keep = false;
-            if (i < cnt) {
-                r = a[ph(i)];
-                const uint32_t b = filter_bit(r >> ish, lo, hashed, LDS_FILTER_BITS);
-                keep = ((rep[b >> 5] >> (b & 31)) & 1u) != 0;
-            }
-            const uint64_t m = ballot(keep);
-            if (m) {
-                uint32_t base = 0;
-                if (lane_id() == 0) base = atomicAdd(&red[RED_CAND], (uint32_t)__builtin_popcountll(m));
-                base = __shfl(base, 0);
-                const uint32_t pos = base + mbcnt(m);
-                if (keep && pos < LDS_FCAP) surv[pos] = r;
-            }
-        }
-        __syncthreads();
-        const uint32_t nc = red[RED_CAND];
-        if (nc == 0) return false;
-        if (nc <= HT_MAX) return hash_decide<NT>(surv, false, nc, tb, a, red, key, i1, i2);
-        if (nc <= LDS_FCAP) {
-            uint32_t np = NT;
-            while (np < nc) np <<= 1;
-            for (uint32_t k = threadIdx.x; k < np; k += NT) a[ph(k)] = k < nc ? surv[k] : ~0ull;
-            n_sort = np;
-            cnt_sort = nc;
-        }
-        // otherwise the group's records are still in place: all are sorted
-    }
-    if (cnt_sort == cnt)
-        for (uint32_t k = cnt + threadIdx.x; k < npow; k += NT) a[ph(k)] = ~0ull;
-    __syncthreads();
-    return sort_scan<NT>(a, n_sort, cnt_sort, tb, red, key, i1, i2);
-}
 
 // Compiled leaves in the fused kernel: at the start of a unit the
 // workgroup evaluates, for the iterations the unit covers of each of the
@@ -1556,28 +1482,20 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 __syncthreads();
                 continue;
             }
-            uint32_t npow = WG;
-            while (npow < cnt) npow <<= 1;
+            // the records move to registers (lanes past the end copy a real
+            // one) and the whole LDS array becomes the decision's scratch
+            constexpr int FE = TILE / WG;
+            unsigned long long v[FE];
+#pragma unroll
+            for (int jj = 0; jj < FE; jj++) {
+                const uint32_t i = (uint32_t)jj * WG + threadIdx.x;
+                if ((uint32_t)jj * WG < cnt) v[jj] = lds_rec[ph(i < cnt ? i : cnt - 1)];
+                else v[jj] = v[0];
+            }
+            __syncthreads();
             unsigned long long key = 0;
             uint32_t r1 = 0, r2 = 0;
-            bool f;
-            if (npow <= (uint32_t)FUSED_PACK) {
-                f = decide_lds<WG>(lds_rec, cnt, npow, tb, lds_res, key, r1, r2);
-            } else {
-                // one phase above FUSED_PACK events leaves no LDS scratch:
-                // its records move to registers (lanes past the end copy the
-                // last one) and the whole array becomes the scratch of the
-                // table / filter / sort decision
-                constexpr int FE = TILE / WG;
-                unsigned long long v[FE];
-#pragma unroll
-                for (int j = 0; j < FE; j++) {
-                    const uint32_t i = (uint32_t)j * WG + threadIdx.x;
-                    v[j] = lds_rec[ph(i < cnt ? i : cnt - 1)];
-                }
-                __syncthreads();
-                f = decide<FE, WG>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
-            }
+            const bool f = decide<FE, WG>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
             if (f && !have) {
                 have = true;
                 const uint64_t kk = gk0 + (pack ? (key >> pd.ib) : 0ull);
