@@ -1381,7 +1381,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
         uint64_t k = u.k0;
         while (k < u.k1) {
             // one group of consecutive phases whose events fit one tile
-            const uint64_t gk0 = k;
+            uint64_t gk0 = k;
             if (threadIdx.x == 0) lds_n = 0;
             __syncthreads();
             uint32_t est = 0, before = 0;
@@ -1390,12 +1390,17 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 uint32_t c;
                 if (!stat) {
                     const unsigned long long ck = phase_counts[k];
-                    if (ck == 0 || ck > (unsigned long long)tile) { k++; continue; }   // empty or in HBM
+                    if (ck == 0 || ck > (unsigned long long)tile) {   // empty or in HBM
+                        k++;
+                        if (!any) gk0 = k;
+                        continue;
+                    }
                     c = (uint32_t)ck;
                 } else {
                     c = pd.phase_bound;
                 }
-                if (any && (!pack || est + c > (uint32_t)FUSED_PACK)) break;
+                // a packed group's phases must fit the key bits above the index
+                if (any && (!pack || est + c > (uint32_t)FUSED_PACK || ((k - gk0) >> (64 - psh)) != 0)) break;
                 const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
                 for (uint32_t ni = 0; ni < pd.nnests; ni++) {
                     const NestDesc &nd = nests[pd.nest0 + ni];

@@ -10,7 +10,7 @@ namespace drf {
 constexpr int WG = 256;            // lanes per workgroup of the evaluator kernels
 constexpr int MAXSPAN = 2048;      // phases one count / emit item may cover
 constexpr int TILE = 8192;         // access events one LDS tile holds (64 KiB)
-constexpr int FUSED_PACK = 4096;   // events of a fused group of several phases (LDS scratch beside it)
+constexpr int FUSED_PACK = 8192;   // events of a fused group of several phases
 constexpr int CHUNK = 4096;        // records per partition chunk (one workgroup)
 constexpr int RADIX = 1024;        // largest partition digit: 10 bits (starts stride per segment)
 constexpr uint32_t FILTER_BITS = 18; // tiles spanning at most 2^18 index values can drop singleton indices
