@@ -55,7 +55,7 @@ enum : uint32_t {
 // are a chain of operations applied to tid, each with a tid-free operand.
 // The tid-free operands ("uniform slots") are evaluated once per iteration;
 // each lane then runs its short chain.  Layout (words, from cal_off):
-//   nacc nuni
+//   nacc nuni acc_off (offset of the first access block from cal_off)
 //   nuni x { len <postfix X_* code over loop variables> }
 //   nacc x { mode form c0 m0k m0 a us pk pa nops { opw arg } * nops }
 // opw = C_* | (C_UNI if arg is a uniform slot, else arg is the immediate).

@@ -904,6 +904,8 @@ struct Planner {
         const int at = (int)c.size();
         c.push_back((uint32_t)accs.size());
         c.push_back((uint32_t)slots.size());
+        const size_t acc_at = c.size();
+        c.push_back(0);   // word offset of the first access block, set below
         for (auto &sl : slots) {
             const size_t len_at = c.size();
             c.push_back(0);
@@ -920,6 +922,7 @@ struct Planner {
                 return -1;
             }
         }
+        c[acc_at] = (uint32_t)(c.size() - (size_t)at);
         for (size_t j = 0; j < accs.size(); j++) {
             // the fixed form: [ADD c0] [AND|MOD m0] [MUL a] [ADD uniform] [AND|MOD pa]
             // form c0 m0k m0 a us pk pa (mode before, nops after: CAL_HDR words in all)

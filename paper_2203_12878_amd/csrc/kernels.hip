@@ -326,13 +326,28 @@ DEV uint64_t phase_of(const NestDesc &nd, uint64_t f) {
 }
 
 // First iteration whose phase is >= k (phases are non-decreasing in f).
+// First iteration of the nest whose phase is at least k (iters if none).
+// One iteration of loop l runs every iteration of the loops inside it, so
+// its stride is at least the phases those can add (rem below) and the
+// phase map is monotone: digits are chosen outermost first, each the least
+// that still lets the inner loops reach k.
 DEV uint64_t first_iter_at(const NestDesc &nd, uint64_t k) {
-    uint64_t lo = 0, hi = nd.iters;
-    while (lo < hi) {
-        uint64_t mid = lo + (hi - lo) / 2;
-        if (phase_of(nd, mid) < k) lo = mid + 1; else hi = mid;
+    if (k <= nd.phase_base) return 0;
+    if (k > nd.phase_last) return nd.iters;
+    uint64_t rem = 0;
+    for (uint32_t l = 0; l < nd.nloops; l++) rem += (nd.trip[l] - 1) * nd.stride[l];
+    uint64_t p = nd.phase_base, f = 0;
+    for (uint32_t l = 0; l < nd.nloops; l++) {
+        rem -= (nd.trip[l] - 1) * nd.stride[l];   // what the loops inside l can add
+        uint64_t d = 0;
+        if (nd.stride[l] && p + rem < k) {
+            d = (k - p - rem + nd.stride[l] - 1) / nd.stride[l];
+            if (d > nd.trip[l] - 1) d = nd.trip[l] - 1;
+        }
+        p += d * nd.stride[l];
+        f = f * nd.trip[l] + d;
     }
-    return lo;
+    return f;
 }
 
 // ============================================================= count pass
@@ -493,12 +508,12 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
     const uint32_t *cal = code + nd.cal_off;
     const uint32_t nacc = rfl(cal[0]), nuni = rfl(cal[1]);
     if (threadIdx.x == 0) {
-        uint32_t o = 2;
+        uint32_t o = 3;
         for (uint32_t z = 0; z < nuni; z++) {
             L.uoff[z] = o;
             o += 1 + cal[o];
         }
-        L.uoff[CAL_MAXU] = o;
+        L.uoff[CAL_MAXU] = cal[2];
     }
     __syncthreads();
     const uint32_t *acc0 = cal + rfl(L.uoff[CAL_MAXU]);
@@ -1330,25 +1345,35 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
         const uint32_t ncache = pd.nnests < FN_CACHE ? pd.nnests : FN_CACHE;
         for (uint32_t ni = lane_id(); ni < ncache; ni += 64) nf[ni] = first_iter_at(nests[pd.nest0 + ni], u.k0);
         if constexpr (!WIDE) {
-            if (threadIdx.x == 0) {
-                uint32_t off = 0;
-                for (uint32_t ni = 0; ni < ncache; ni++) {
+            if (threadIdx.x < 64) {
+                // wave 0 plans the staging, lane ni for nest ni; nests are
+                // staged in order while their words fit
+                const uint32_t ni = threadIdx.x;
+                uint32_t need = 0, acc = 0;
+                uint64_t fa = 0, fb = 0;
+                if (ni < ncache) {
                     const NestDesc &nd = nests[pd.nest0 + ni];
-                    lds_st.base[ni] = NONE32;
-                    if (nd.cal_off == NONE32 || u.k1 <= nd.phase_base || u.k0 > nd.phase_last) continue;
-                    const uint64_t fa = first_iter_at(nd, u.k0), fb = first_iter_at(nd, u.k1);
-                    if (fb <= fa) continue;
-                    const uint32_t *cal = code + nd.cal_off;
-                    const uint32_t nuni = cal[1];
-                    const uint64_t need = (2 + (uint64_t)nuni) * (fb - fa);
-                    if (off + need > STAGE_WORDS) continue;
-                    uint32_t o = 2;
-                    for (uint32_t z = 0; z < nuni; z++) o += 1 + cal[o];
-                    lds_st.base[ni] = off;
+                    if (nd.cal_off != NONE32 && u.k1 > nd.phase_base && u.k0 <= nd.phase_last) {
+                        fa = first_iter_at(nd, u.k0);
+                        fb = first_iter_at(nd, u.k1);
+                        const uint32_t *cal = code + nd.cal_off;
+                        const uint64_t w = (2 + (uint64_t)cal[1]) * (fb - fa);
+                        if (fb > fa && w <= STAGE_WORDS) {
+                            need = (uint32_t)w;
+                            acc = cal[2];
+                        }
+                    }
+                }
+                uint32_t inc = need;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(inc, (unsigned)o);
+                    if ((int)lane_id() >= o) inc += y;
+                }
+                if (ni < ncache) {
+                    lds_st.base[ni] = (need && inc <= STAGE_WORDS) ? inc - need : NONE32;
                     lds_st.cnt[ni] = (uint32_t)(fb - fa);
-                    lds_st.acc[ni] = o;
+                    lds_st.acc[ni] = acc;
                     lds_st.f0[ni] = fa;
-                    off += (uint32_t)need;
                 }
             }
             __syncthreads();
@@ -1367,7 +1392,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     odo.start(nd, lds_st.f0[ni] + fi, vars);
                     lds_st.w[sb + fi] = (uint32_t)(odo.phase - u.k0);
                     lds_st.w[sb + cs + fi] = tid_limit<T>(nd, code, vars, pd.n);
-                    const uint32_t *up = cal + 2;
+                    const uint32_t *up = cal + 3;
                     for (uint32_t z = 0; z < nuni; z++) {
                         bool o = false;
                         const uint32_t len = rfl(up[0]);
