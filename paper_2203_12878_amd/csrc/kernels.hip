@@ -1301,6 +1301,7 @@ struct FusedStage {
     uint32_t cnt[FN_CACHE];             // staged iterations
     uint32_t acc[FN_CACHE];             // word offset of the access blocks in the compiled leaf
     unsigned long long f0[FN_CACHE];    // first staged iteration
+    uint32_t all;                       // every nest with iterations in the unit is staged
     uint32_t w[STAGE_WORDS];            // per nest: phase - k0, thread limit, then each slot (cnt words each)
 };
 
@@ -1351,16 +1352,20 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 const uint32_t ni = threadIdx.x;
                 uint32_t need = 0, acc = 0;
                 uint64_t fa = 0, fb = 0;
-                if (ni < ncache) {
+                bool active = false;
+                if (ni < pd.nnests) {
                     const NestDesc &nd = nests[pd.nest0 + ni];
-                    if (nd.cal_off != NONE32 && u.k1 > nd.phase_base && u.k0 <= nd.phase_last) {
+                    if (u.k1 > nd.phase_base && u.k0 <= nd.phase_last) {
                         fa = first_iter_at(nd, u.k0);
                         fb = first_iter_at(nd, u.k1);
-                        const uint32_t *cal = code + nd.cal_off;
-                        const uint64_t w = (2 + (uint64_t)cal[1]) * (fb - fa);
-                        if (fb > fa && w <= STAGE_WORDS) {
-                            need = (uint32_t)w;
-                            acc = cal[2];
+                        active = fb > fa;
+                        if (active && ni < ncache && nd.cal_off != NONE32) {
+                            const uint32_t *cal = code + nd.cal_off;
+                            const uint64_t w = (2 + (uint64_t)cal[1]) * (fb - fa);
+                            if (w <= STAGE_WORDS) {
+                                need = (uint32_t)w;
+                                acc = cal[2];
+                            }
                         }
                     }
                 }
@@ -1369,12 +1374,15 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     const uint32_t y = __shfl_up(inc, (unsigned)o);
                     if ((int)lane_id() >= o) inc += y;
                 }
+                const bool staged = need && inc <= STAGE_WORDS;
                 if (ni < ncache) {
-                    lds_st.base[ni] = (need && inc <= STAGE_WORDS) ? inc - need : NONE32;
+                    lds_st.base[ni] = staged ? inc - need : NONE32;
                     lds_st.cnt[ni] = (uint32_t)(fb - fa);
                     lds_st.acc[ni] = acc;
                     lds_st.f0[ni] = fa;
                 }
+                const bool all = ballot(active && !staged) == 0 && pd.nnests <= 64;
+                if (ni == 0) lds_st.all = all ? 1u : 0u;
             }
             __syncthreads();
             for (uint32_t ni = 0; ni < ncache; ni++) {
@@ -1403,13 +1411,19 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             }
             __syncthreads();
         }
+        // When every nest with iterations in the unit is staged, each active
+        // lane writes exactly nacc records per iteration: record positions
+        // follow from the (uniform) running count and per-phase counts from
+        // arithmetic, with no atomics and no barrier per phase.
+        bool fast = false;
+        if constexpr (!WIDE) fast = lds_st.all != 0;
         uint64_t k = u.k0;
         while (k < u.k1) {
             // one group of consecutive phases whose events fit one tile
             uint64_t gk0 = k;
             if (threadIdx.x == 0) lds_n = 0;
             __syncthreads();
-            uint32_t est = 0, before = 0;
+            uint32_t est = 0, before = 0, off = 0;
             bool any = false;
             while (k < u.k1) {
                 uint32_t c;
@@ -1443,6 +1457,34 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                             for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
                                 const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
                                 const uint32_t *U = lds_st.w + sb + 2 * cs + i;
+                                if (fast) {
+                                    // active tids are [0, L): wave w writes after the
+                                    // records of the tids of the waves before it
+                                    const uint32_t L = lim < pd.n ? lim : pd.n;
+                                    const uint32_t wv = threadIdx.x >> 6, lane = lane_id();
+                                    for (uint32_t t0 = 0; t0 < L; t0 += WG) {
+                                        const uint32_t left = L - t0;
+                                        const uint32_t bw = left < 64 * wv ? left : 64 * wv;
+                                        const uint32_t na = left - bw < 64 ? left - bw : 64;
+                                        if (na) {
+                                            const uint32_t tid = t0 + threadIdx.x;
+                                            const uint32_t p0 = off + nacc * bw + lane;
+                                            const uint32_t *ap = acc0;
+                                            for (uint32_t j = 0; j < nacc; j++) {
+                                                const uint32_t mode = rfl(ap[0]);
+                                                const uint32_t v = cal_index(ap, tid, U, cs);
+                                                const uint32_t pos = p0 + j * na;
+                                                if (lane < na && pos < (uint32_t)TILE)
+                                                    lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
+                                                                       ((unsigned long long)tid << 1) | mode;
+                                                ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
+                                            }
+                                        }
+                                        off += nacc * (left < (uint32_t)WG ? left : (uint32_t)WG);
+                                    }
+                                    before += nacc * L;
+                                    continue;
+                                }
                                 for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
                                     const uint32_t tid = t0 + threadIdx.x;
                                     const bool act = tid < pd.n && tid < lim;
@@ -1492,7 +1534,11 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     }
                     if (ni < ncache) nf[ni] = f;
                 }
-                if (stat) {
+                if (stat && fast) {
+                    // before: this phase's records (counted as written)
+                    if (threadIdx.x == 0) phase_counts[k] = before;
+                    before = 0;
+                } else if (stat) {
                     __syncthreads();
                     const uint32_t now = lds_n;
                     if (threadIdx.x == 0) phase_counts[k] = now - before;
@@ -1505,7 +1551,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             }
             if (!any) break;
             __syncthreads();
-            uint32_t cnt = lds_n;
+            uint32_t cnt = fast ? off : lds_n;
             total += cnt;
             if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: bounded by count or plan
             if (cnt == 0) {
