@@ -1296,14 +1296,40 @@ struct FusedSink {
 // limit and every uniform slot, one iteration per lane.  Each phase then
 // only runs the lanes' access chains.
 constexpr uint32_t STAGE_WORDS = 2048;
+// Each staged nest also gets its access headers decoded into w (HSTRIDE
+// words each: the fixed-form words and op count of the compiled access,
+// then the offset of its op list in the code blob), and the nests with
+// iterations in the unit are listed (act_*) when all of them are staged.
+constexpr uint32_t HSTRIDE = 12;
+static_assert(CAL_HDR + 1 <= HSTRIDE, "decoded access header");
 struct FusedStage {
     uint32_t base[FN_CACHE];            // first word of the nest's block in w, or NONE32 (not staged)
     uint32_t cnt[FN_CACHE];             // staged iterations
     uint32_t acc[FN_CACHE];             // word offset of the access blocks in the compiled leaf
     unsigned long long f0[FN_CACHE];    // first staged iteration
     uint32_t all;                       // every nest with iterations in the unit is staged
-    uint32_t w[STAGE_WORDS];            // per nest: phase - k0, thread limit, then each slot (cnt words each)
+    uint32_t nact;                      // ... and how many there are
+    uint32_t act_ni[FN_CACHE], act_sb[FN_CACHE], act_cs[FN_CACHE], act_nacc[FN_CACHE], act_hofs[FN_CACHE];
+    uint32_t w[STAGE_WORDS];            // per nest: phase - k0, thread limit, each slot (cnt words each), headers
 };
+
+// Index of one compiled access whose header was decoded to LDS at hp.
+DEV uint32_t cal_index_hdr(const uint32_t *hp, const uint32_t *__restrict__ code, uint32_t tid, const uint32_t *U,
+                           uint32_t ustride) {
+    if (rfl(hp[1]) == 1u) {
+        const uint32_t c0 = rfl(hp[2]), m0k = rfl(hp[3]), m0 = rfl(hp[4]), a = rfl(hp[5]), us = rfl(hp[6]);
+        const uint32_t pk = rfl(hp[7]), pa = rfl(hp[8]);
+        uint32_t v = tid + c0;
+        if (m0k == CAL_K_AND) v &= m0;
+        else if (m0k == CAL_K_MOD) v = m0 ? v % m0 : v;
+        v *= a;
+        if (us != NONE32) v += rfl(U[us * ustride]);
+        if (pk == CAL_K_AND) v &= pa;
+        else if (pk == CAL_K_MOD) v = pa ? v % pa : v;
+        return v;
+    }
+    return cal_chain(code + rfl(hp[10]), rfl(hp[9]), tid, U, ustride);
+}
 
 template <typename T, bool WIDE>
 DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
@@ -1321,7 +1347,11 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
     // first FN_CACHE nests (each wave reads only its own row: no barrier)
     __shared__ unsigned long long lds_nf[WG / 64][FN_CACHE];
     __shared__ FusedStage lds_st;
+    // per wave, in the all-staged mode: each listed nest's next staged
+    // iteration, and the first one past the current phase
+    __shared__ uint32_t lds_cur[WG / 64][FN_CACHE], lds_nx[WG / 64][FN_CACHE];
     unsigned long long *nf = lds_nf[threadIdx.x >> 6];
+    uint32_t *cur = lds_cur[threadIdx.x >> 6], *nx = lds_nx[threadIdx.x >> 6];
     // persistent: workgroups pull units (largest first) from a device queue
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1350,7 +1380,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 // wave 0 plans the staging, lane ni for nest ni; nests are
                 // staged in order while their words fit
                 const uint32_t ni = threadIdx.x;
-                uint32_t need = 0, acc = 0;
+                uint32_t need = 0, acc = 0, nacc = 0, nuni = 0;
                 uint64_t fa = 0, fb = 0;
                 bool active = false;
                 if (ni < pd.nnests) {
@@ -1361,7 +1391,9 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                         active = fb > fa;
                         if (active && ni < ncache && nd.cal_off != NONE32) {
                             const uint32_t *cal = code + nd.cal_off;
-                            const uint64_t w = (2 + (uint64_t)cal[1]) * (fb - fa);
+                            nacc = cal[0];
+                            nuni = cal[1];
+                            const uint64_t w = (2 + (uint64_t)nuni) * (fb - fa) + (uint64_t)HSTRIDE * nacc;
                             if (w <= STAGE_WORDS) {
                                 need = (uint32_t)w;
                                 acc = cal[2];
@@ -1382,7 +1414,19 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     lds_st.f0[ni] = fa;
                 }
                 const bool all = ballot(active && !staged) == 0 && pd.nnests <= 64;
-                if (ni == 0) lds_st.all = all ? 1u : 0u;
+                const uint64_t sm = ballot(staged);
+                if (staged) {
+                    const uint32_t a = mbcnt(sm);
+                    lds_st.act_ni[a] = ni;
+                    lds_st.act_sb[a] = inc - need;
+                    lds_st.act_cs[a] = (uint32_t)(fb - fa);
+                    lds_st.act_nacc[a] = nacc;
+                    lds_st.act_hofs[a] = inc - need + (2 + nuni) * (uint32_t)(fb - fa);
+                }
+                if (ni == 0) {
+                    lds_st.all = all ? 1u : 0u;
+                    lds_st.nact = (uint32_t)__builtin_popcountll(sm);
+                }
             }
             __syncthreads();
             for (uint32_t ni = 0; ni < ncache; ni++) {
@@ -1409,6 +1453,19 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     }
                 }
             }
+            // decoded access headers of the staged nests, a thread per nest
+            if (threadIdx.x < lds_st.nact) {
+                const uint32_t a = threadIdx.x;
+                const uint32_t *cal = code + nests[pd.nest0 + lds_st.act_ni[a]].cal_off;
+                const uint32_t *ap = cal + cal[2];
+                uint32_t *hp = lds_st.w + lds_st.act_hofs[a];
+                for (uint32_t j = 0; j < lds_st.act_nacc[a]; j++) {
+                    for (uint32_t q = 0; q < CAL_HDR; q++) hp[q] = ap[q];
+                    hp[CAL_HDR] = (uint32_t)(ap + CAL_HDR - code);
+                    ap += CAL_HDR + 2 * ap[CAL_HDR - 1];
+                    hp += HSTRIDE;
+                }
+            }
             __syncthreads();
         }
         // When every nest with iterations in the unit is staged, each active
@@ -1416,7 +1473,12 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
         // follow from the (uniform) running count and per-phase counts from
         // arithmetic, with no atomics and no barrier per phase.
         bool fast = false;
-        if constexpr (!WIDE) fast = lds_st.all != 0;
+        uint32_t nact = 0;
+        if constexpr (!WIDE) {
+            fast = lds_st.all != 0;
+            nact = lds_st.nact;
+            for (uint32_t a = lane_id(); a < nact; a += 64) cur[a] = 0;
+        }
         uint64_t k = u.k0;
         while (k < u.k1) {
             // one group of consecutive phases whose events fit one tile
@@ -1427,7 +1489,27 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             bool any = false;
             while (k < u.k1) {
                 uint32_t c;
-                if (!stat) {
+                if (fast) {
+                    // exact records of phase k: the staged iterations at k
+                    const uint32_t kr = (uint32_t)(k - u.k0);
+                    c = 0;
+                    for (uint32_t a = 0; a < nact; a++) {
+                        const uint32_t sb = rfl(lds_st.act_sb[a]), cs = rfl(lds_st.act_cs[a]);
+                        const uint32_t na = rfl(lds_st.act_nacc[a]);
+                        uint32_t i = rfl(cur[a]);
+                        for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
+                            const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
+                            c += na * (lim < pd.n ? lim : pd.n);
+                        }
+                        nx[a] = i;
+                    }
+                    if (c == 0 || c > tile) {   // no records, or in HBM
+                        for (uint32_t a = lane_id(); a < nact; a += 64) cur[a] = nx[a];
+                        k++;
+                        if (!any) gk0 = k;
+                        continue;
+                    }
+                } else if (!stat) {
                     const unsigned long long ck = phase_counts[k];
                     if (ck == 0 || ck > (unsigned long long)tile) {   // empty or in HBM
                         k++;
@@ -1441,6 +1523,48 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                 // a packed group's phases must fit the key bits above the index
                 if (any && (!pack || est + c > (uint32_t)FUSED_PACK || ((k - gk0) >> (64 - psh)) != 0)) break;
                 const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
+                if (fast) {
+                    for (uint32_t a = 0; a < nact; a++) {
+                        const uint32_t sb = rfl(lds_st.act_sb[a]), cs = rfl(lds_st.act_cs[a]);
+                        const uint32_t nacc = rfl(lds_st.act_nacc[a]);
+                        const uint32_t *hp0 = lds_st.w + rfl(lds_st.act_hofs[a]);
+                        const uint32_t i1 = rfl(nx[a]);
+                        for (uint32_t i = rfl(cur[a]); i < i1; i++) {
+                            const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
+                            const uint32_t *U = lds_st.w + sb + 2 * cs + i;
+                            // active tids are [0, L): wave w writes after the
+                            // records of the tids of the waves before it
+                            const uint32_t L = lim < pd.n ? lim : pd.n;
+                            const uint32_t wv = threadIdx.x >> 6, lane = lane_id();
+                            for (uint32_t t0 = 0; t0 < L; t0 += WG) {
+                                const uint32_t left = L - t0;
+                                const uint32_t bw = left < 64 * wv ? left : 64 * wv;
+                                const uint32_t na = left - bw < 64 ? left - bw : 64;
+                                if (na) {
+                                    const uint32_t tid = t0 + threadIdx.x;
+                                    const uint32_t p0 = off + nacc * bw + lane;
+                                    const uint32_t *hp = hp0;
+                                    for (uint32_t j = 0; j < nacc; j++) {
+                                        const uint32_t mode = rfl(hp[0]);
+                                        const uint32_t v = cal_index_hdr(hp, code, tid, U, cs);
+                                        const uint32_t pos = p0 + j * na;
+                                        if (lane < na && pos < (uint32_t)TILE)
+                                            lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
+                                                               ((unsigned long long)tid << 1) | mode;
+                                        hp += HSTRIDE;
+                                    }
+                                }
+                                off += nacc * (left < (uint32_t)WG ? left : (uint32_t)WG);
+                            }
+                        }
+                        cur[a] = i1;
+                    }
+                    if (stat && threadIdx.x == 0) phase_counts[k] = c;
+                    est += c;
+                    any = true;
+                    k++;
+                    continue;
+                }
                 for (uint32_t ni = 0; ni < pd.nnests; ni++) {
                     const NestDesc &nd = nests[pd.nest0 + ni];
                     if (k < nd.phase_base || k > nd.phase_last) continue;
@@ -1457,34 +1581,6 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                             for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
                                 const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
                                 const uint32_t *U = lds_st.w + sb + 2 * cs + i;
-                                if (fast) {
-                                    // active tids are [0, L): wave w writes after the
-                                    // records of the tids of the waves before it
-                                    const uint32_t L = lim < pd.n ? lim : pd.n;
-                                    const uint32_t wv = threadIdx.x >> 6, lane = lane_id();
-                                    for (uint32_t t0 = 0; t0 < L; t0 += WG) {
-                                        const uint32_t left = L - t0;
-                                        const uint32_t bw = left < 64 * wv ? left : 64 * wv;
-                                        const uint32_t na = left - bw < 64 ? left - bw : 64;
-                                        if (na) {
-                                            const uint32_t tid = t0 + threadIdx.x;
-                                            const uint32_t p0 = off + nacc * bw + lane;
-                                            const uint32_t *ap = acc0;
-                                            for (uint32_t j = 0; j < nacc; j++) {
-                                                const uint32_t mode = rfl(ap[0]);
-                                                const uint32_t v = cal_index(ap, tid, U, cs);
-                                                const uint32_t pos = p0 + j * na;
-                                                if (lane < na && pos < (uint32_t)TILE)
-                                                    lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
-                                                                       ((unsigned long long)tid << 1) | mode;
-                                                ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
-                                            }
-                                        }
-                                        off += nacc * (left < (uint32_t)WG ? left : (uint32_t)WG);
-                                    }
-                                    before += nacc * L;
-                                    continue;
-                                }
                                 for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
                                     const uint32_t tid = t0 + threadIdx.x;
                                     const bool act = tid < pd.n && tid < lim;
@@ -1534,11 +1630,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     }
                     if (ni < ncache) nf[ni] = f;
                 }
-                if (stat && fast) {
-                    // before: this phase's records (counted as written)
-                    if (threadIdx.x == 0) phase_counts[k] = before;
-                    before = 0;
-                } else if (stat) {
+                if (stat) {
                     __syncthreads();
                     const uint32_t now = lds_n;
                     if (threadIdx.x == 0) phase_counts[k] = now - before;
