@@ -1313,22 +1313,41 @@ struct FusedStage {
     uint32_t w[STAGE_WORDS];            // per nest: phase - k0, thread limit, each slot (cnt words each), headers
 };
 
-// Index of one compiled access whose header was decoded to LDS at hp.
-DEV uint32_t cal_index_hdr(const uint32_t *hp, const uint32_t *__restrict__ code, uint32_t tid, const uint32_t *U,
-                           uint32_t ustride) {
-    if (rfl(hp[1]) == 1u) {
-        const uint32_t c0 = rfl(hp[2]), m0k = rfl(hp[3]), m0 = rfl(hp[4]), a = rfl(hp[5]), us = rfl(hp[6]);
-        const uint32_t pk = rfl(hp[7]), pa = rfl(hp[8]);
+// Index of one compiled access whose header was decoded to LDS at hp, for
+// a header that may differ between lanes.
+DEV uint32_t cal_index_lane(const uint32_t *hp, const uint32_t *__restrict__ code, uint32_t tid, const uint32_t *U,
+                            uint32_t ustride) {
+    if (hp[1] == 1u) {
+        const uint32_t c0 = hp[2], m0k = hp[3], m0 = hp[4], a = hp[5], us = hp[6], pk = hp[7], pa = hp[8];
         uint32_t v = tid + c0;
         if (m0k == CAL_K_AND) v &= m0;
         else if (m0k == CAL_K_MOD) v = m0 ? v % m0 : v;
         v *= a;
-        if (us != NONE32) v += rfl(U[us * ustride]);
+        if (us != NONE32) v += U[us * ustride];
         if (pk == CAL_K_AND) v &= pa;
         else if (pk == CAL_K_MOD) v = pa ? v % pa : v;
         return v;
     }
-    return cal_chain(code + rfl(hp[10]), rfl(hp[9]), tid, U, ustride);
+    const uint32_t *op = code + hp[10];
+    uint32_t v = tid;
+    for (uint32_t o = 0; o < hp[9]; o++) {
+        const uint32_t opw = op[2 * o], arg = op[2 * o + 1];
+        const uint32_t x = (opw & C_UNI) ? U[arg * ustride] : arg;
+        switch (opw & 0xFFu) {
+        case C_ADD: v += x; break;
+        case C_MUL: v *= x; break;
+        case C_MONUS: v = v > x ? v - x : 0u; break;
+        case C_RMONUS: v = x > v ? x - v : 0u; break;
+        case C_DIV: v = x ? v / x : 0u; break;
+        case C_MOD: v = x ? v % x : v; break;
+        case C_SHL: v = x >= 32u ? 0u : v << x; break;
+        case C_SHR: v = x >= 32u ? 0u : v >> x; break;
+        case C_MIN: v = v < x ? v : x; break;
+        case C_MAX: v = v > x ? v : x; break;
+        default: v &= x; break;   // C_AND
+        }
+    }
+    return v;
 }
 
 template <typename T, bool WIDE>
@@ -1532,30 +1551,28 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                         for (uint32_t i = rfl(cur[a]); i < i1; i++) {
                             const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
                             const uint32_t *U = lds_st.w + sb + 2 * cs + i;
-                            // active tids are [0, L): wave w writes after the
-                            // records of the tids of the waves before it
+                            // active tids are [0, L); the iteration's L * nacc
+                            // records are spread over the lanes, access-major:
+                            // record e is access e / L of tid e % L (the
+                            // division by a multiply-high, exact since e and L
+                            // are at most one tile)
                             const uint32_t L = lim < pd.n ? lim : pd.n;
-                            const uint32_t wv = threadIdx.x >> 6, lane = lane_id();
-                            for (uint32_t t0 = 0; t0 < L; t0 += WG) {
-                                const uint32_t left = L - t0;
-                                const uint32_t bw = left < 64 * wv ? left : 64 * wv;
-                                const uint32_t na = left - bw < 64 ? left - bw : 64;
-                                if (na) {
-                                    const uint32_t tid = t0 + threadIdx.x;
-                                    const uint32_t p0 = off + nacc * bw + lane;
-                                    const uint32_t *hp = hp0;
-                                    for (uint32_t j = 0; j < nacc; j++) {
-                                        const uint32_t mode = rfl(hp[0]);
-                                        const uint32_t v = cal_index_hdr(hp, code, tid, U, cs);
-                                        const uint32_t pos = p0 + j * na;
-                                        if (lane < na && pos < (uint32_t)TILE)
-                                            lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
-                                                               ((unsigned long long)tid << 1) | mode;
-                                        hp += HSTRIDE;
-                                    }
+                            const uint32_t R = L * nacc;
+                            const uint32_t M = L > 1 ? (uint32_t)(0xFFFFFFFFull / L) + 1u : 0u;
+                            for (uint32_t e0 = 0; e0 < R; e0 += WG) {
+                                const uint32_t e = e0 + threadIdx.x;
+                                if (e < R) {
+                                    const uint32_t j = L > 1 ? __umulhi(e, M) : e;
+                                    const uint32_t tid = e - j * L;
+                                    const uint32_t *hp = hp0 + j * HSTRIDE;
+                                    const uint32_t v = cal_index_lane(hp, code, tid, U, cs);
+                                    const uint32_t pos = off + e;
+                                    if (pos < (uint32_t)TILE)
+                                        lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
+                                                           ((unsigned long long)tid << 1) | hp[0];
                                 }
-                                off += nacc * (left < (uint32_t)WG ? left : (uint32_t)WG);
                             }
+                            off += R;
                         }
                         cur[a] = i1;
                     }
