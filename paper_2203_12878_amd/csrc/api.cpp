@@ -54,6 +54,13 @@ struct drf_ctx {
     hipEvent_t parted = nullptr;        // a partition level's bucket starts are on the host
     void *h_starts = nullptr;           // pinned host copy of those starts
     size_t h_starts_cap = 0;
+    // pinned host staging of uploads and read-backs: blocks kept for the
+    // context's life, handed out in order during a call and reused once the
+    // call's stream has drained
+    std::vector<std::pair<char *, size_t>> pin_blocks;
+    size_t pin_bi = 0, pin_off = 0;
+    void *h_counts = nullptr;           // pinned read-back of per-phase counts and overflow flags
+    size_t h_counts_cap = 0;
     bool done_valid = false;
     uint32_t cus = 256;
     drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 16, 1u << 16};
@@ -175,15 +182,42 @@ void grow(void *&p, size_t &size, size_t need) {
     size = want;
 }
 
-// host copies of uploaded arrays stay alive until the call's next sync
+// Host copies of uploaded arrays (and read-back buffers) in pinned memory,
+// so that copies never wait for the stream; they stay untouched until the
+// call's next stream sync.
 struct Keep {
-    std::vector<std::vector<char>> bufs;
+    drf_ctx *ctx = nullptr;
+    void *take(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        auto &B = ctx->pin_blocks;
+        while (ctx->pin_bi < B.size() && ctx->pin_off + bytes > B[ctx->pin_bi].second) {
+            ctx->pin_bi++;
+            ctx->pin_off = 0;
+        }
+        if (ctx->pin_bi == B.size()) {
+            const size_t want = std::max<size_t>(bytes, B.empty() ? (8u << 20) : 2 * B.back().second);
+            void *p = nullptr;
+            if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                throw Fail{DRF_E_NOMEM};
+            }
+            B.push_back({(char *)p, want});
+            ctx->pin_off = 0;
+        }
+        void *r = B[ctx->pin_bi].first + ctx->pin_off;
+        ctx->pin_off += bytes;
+        return r;
+    }
     template <class T>
     const void *hold(const std::vector<T> &v) {
-        bufs.emplace_back((const char *)v.data(), (const char *)v.data() + v.size() * sizeof(T));
-        return bufs.back().data();
+        void *p = take(v.size() * sizeof(T));
+        memcpy(p, v.data(), v.size() * sizeof(T));
+        return p;
     }
-    void clear() { bufs.clear(); }
+    void clear() {
+        ctx->pin_bi = 0;
+        ctx->pin_off = 0;
+    }
 };
 
 template <class T>
@@ -780,6 +814,8 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
     C.st = st;
     C.count = count;
     C.rec = rec;
+    C.keep.ctx = ctx;
+    C.keep.clear();   // the previous call on this context ended with its stream drained
     try {
         hipck(hipSetDevice(ctx->device));
         if (ctx->done_valid) hipck(hipStreamWaitEvent(st, ctx->done, 0));
@@ -828,9 +864,13 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         auto fused = [&](std::vector<Unit> &units, bool wide, size_t dst_off, const std::vector<uint64_t> &work,
                          uint64_t events) {
             if (units.empty()) return;
-            std::vector<size_t> order(units.size());
-            for (size_t i = 0; i < order.size(); i++) order[i] = i;
-            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+            // largest first by powers of two of the work, in input order
+            // within one power (a counting sort: linear in the units)
+            auto bucket = [](uint64_t w) { return w ? 64 - __builtin_clzll(w) : 0; };
+            std::vector<size_t> start(66, 0), order(units.size());
+            for (uint64_t w : work) start[65 - bucket(w)]++;
+            for (size_t b = 1; b < start.size(); b++) start[b] += start[b - 1];
+            for (size_t i = 0; i < units.size(); i++) order[start[64 - bucket(work[i])]++] = i;
             for (uint64_t b0 = 0; b0 < units.size(); b0 += CAND_CAP) {
                 const uint64_t n = std::min<uint64_t>(units.size() - b0, CAND_CAP);
                 std::vector<Unit> part(n);
@@ -873,13 +913,30 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             }
         }
         C.tr.mark("count launched");
-        std::vector<uint64_t> counts(C.total_phases);
-        std::vector<uint32_t> hovf(count);
+        uint64_t *counts = nullptr;
+        uint32_t *hovf = nullptr;
         if (dynamic) {
+            // pinned read-back buffers of the context (not the upload staging,
+            // which a sync in between may recycle)
+            const size_t need = (std::max<uint64_t>(1, C.total_phases) * sizeof(uint64_t) + 255) & ~(size_t)255;
+            const size_t want = need + count * sizeof(uint32_t);
+            if (want > ctx->h_counts_cap) {
+                if (ctx->h_counts) hipck(hipHostFree(ctx->h_counts));
+                ctx->h_counts = nullptr;
+                ctx->h_counts_cap = 0;
+                if (hipHostMalloc(&ctx->h_counts, want, hipHostMallocDefault) != hipSuccess) {
+                    ctx->h_counts = nullptr;
+                    (void)hipGetLastError();
+                    throw Fail{DRF_E_NOMEM};
+                }
+                ctx->h_counts_cap = want;
+            }
+            counts = (uint64_t *)ctx->h_counts;
+            hovf = (uint32_t *)((char *)ctx->h_counts + need);
             if (C.total_phases)
-                hipck(hipMemcpyAsync(counts.data(), phase_counts, C.total_phases * sizeof(uint64_t),
+                hipck(hipMemcpyAsync(counts, phase_counts, C.total_phases * sizeof(uint64_t),
                                      hipMemcpyDeviceToHost, st));
-            hipck(hipMemcpyAsync(hovf.data(), ovf, count * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            hipck(hipMemcpyAsync(hovf, ovf, count * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             if (!ctx->counted) hipck(hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming));
             hipck(hipEventRecord(ctx->counted, st));
         }
@@ -1106,6 +1163,8 @@ int drf_ctx_destroy(drf_ctx *ctx) {
     if (ctx->counted) (void)hipEventDestroy(ctx->counted);
     if (ctx->parted) (void)hipEventDestroy(ctx->parted);
     if (ctx->h_starts) (void)hipHostFree(ctx->h_starts);
+    for (auto &b : ctx->pin_blocks) (void)hipHostFree(b.first);
+    if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
     for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     delete ctx;
