@@ -1175,37 +1175,45 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         return found;
     }
 
-    // filter: seen / repeated bitmaps, then the survivors: their mask per
-    // thread, and (up to SURV_CAP) a compact copy at a[ph(0..)], below the
-    // repeated bitmap (the seen bitmap is no longer read)
+    // filter: a seen bitmap first (most groups end there: no cell repeats),
+    // then a repeated bitmap, then the survivors: their mask per thread,
+    // and (up to SURV_CAP) a compact copy at a[ph(0..)], below the repeated
+    // bitmap (the seen bitmap is no longer read)
     uint32_t keepm = 0, nc;
     {
         const bool hashed = span > (1ull << FILTER_BITS);
-        const uint32_t nw = hashed ? FILTER_WORDS : (uint32_t)((span + 31) >> 5);
+        // bitmap words, a multiple of four: cleared 16 bytes at a time
+        const uint32_t nw = hashed ? FILTER_WORDS : (((uint32_t)((span + 31) >> 5) + 3u) & ~3u);
         uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
-        for (uint32_t k = threadIdx.x; k < nw; k += NT) {
-            seen[k] = 0;
-            rep[k] = 0;
-        }
+        uint4 *seen4 = reinterpret_cast<uint4 *>(seen), *rep4 = reinterpret_cast<uint4 *>(rep);
+        for (uint32_t q = threadIdx.x; q < nw / 4; q += NT) seen4[q] = make_uint4(0u, 0u, 0u, 0u);
         if (threadIdx.x == 0) {
             red[RED_CAND] = 0;
             red[RED_NC] = 0;
         }
         __syncthreads();
-        bool again = false;
+        // this thread's records whose cell was seen before
+        uint32_t repm = 0;
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if ((uint32_t)j * NT + threadIdx.x < cnt) {
                 const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS), bit = 1u << (b & 31);
-                if (atomicOr(&seen[b >> 5], bit) & bit) {
-                    atomicOr(&rep[b >> 5], bit);
-                    again = true;
-                }
+                if (atomicOr(&seen[b >> 5], bit) & bit) repm |= 1u << j;
             }
         }
-        if (again) red[RED_CAND] = 1;
+        if (repm) red[RED_CAND] = 1;
         __syncthreads();
         if (red[RED_CAND] == 0) return false;   // every cell touched once
+        for (uint32_t q = threadIdx.x; q < nw / 4; q += NT) rep4[q] = make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; j++) {
+            if ((repm >> j) & 1u) {
+                const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
+                atomicOr(&rep[b >> 5], 1u << (b & 31));
+            }
+        }
+        __syncthreads();
 #pragma unroll
         for (int j = 0; j < E; j++) {
             const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
@@ -1357,7 +1365,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     unsigned long long *__restrict__ phase_counts, unsigned long long *__restrict__ nrec,
                     uint32_t *__restrict__ ovf_flags, Cand *__restrict__ cands, Best *__restrict__ best,
                     uint32_t tile) {
-    __shared__ unsigned long long lds_rec[TILE_LDS];
+    __shared__ __align__(16) unsigned long long lds_rec[TILE_LDS];
     __shared__ uint32_t lds_n;
     __shared__ uint32_t lds_res[RED_WORDS];
     __shared__ uint32_t lds_unit;
@@ -1896,7 +1904,7 @@ DEV void tile_run(const Tile &t, const unsigned long long *__restrict__ src, uns
 __global__ __launch_bounds__(TWG) __attribute__((amdgpu_waves_per_eu(4))) void k_tile(
     const Tile *__restrict__ tiles, const unsigned long long *__restrict__ recs, Cand *__restrict__ cands,
     Best *__restrict__ best) {
-    __shared__ unsigned long long lds_rec[TILE_LDS];
+    __shared__ __align__(16) unsigned long long lds_rec[TILE_LDS];
     __shared__ uint32_t lds_res[RED_WORDS];
     const Tile t = tiles[blockIdx.x];
     Cand *my = &cands[blockIdx.x];
