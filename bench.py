@@ -143,13 +143,16 @@ def compare_paths(drf, chk):
             "speedup": round(out["plain"] / out["batched"], 3)}
 
 
-def serving(rates, horizon_s=1.0):
+def serving(rates, requests_per_rate=5000):
     """Poisson streams of check requests through the continuous-batching
-    server: latency percentiles and throughput per offered rate."""
+    server: latency percentiles and throughput per offered rate.  Each
+    stream lasts about requests_per_rate / rate seconds (one second at
+    most)."""
     from paper_2203_12878_amd import workloads as w
     from paper_2203_12878_amd.server import Server, run_stream
     rows = []
     for rate in rates:
+        horizon_s = min(1.0, requests_per_rate / rate)
         reqs = w.gen_requests(rate=float(rate), max_requests=int(rate * horizon_s * 2), horizon_s=horizon_s)
         with Server(device=0, workers=2, budget_bytes=8 << 30) as srv:
             res, wall = run_stream(srv, reqs)
@@ -277,7 +280,7 @@ def main():
         line["cpu_baseline"] = cb
     if not args.no_extras:
         line["batched_vs_plain"] = compare_paths(drf, chk)
-        line["serving"] = serving([1000, 5000])
+        line["serving"] = serving([1000, 5000, 20000, 50000])
     print(json.dumps(line), flush=True)
     chk.close()
 
