@@ -133,7 +133,7 @@ class CheckResult:
     status: int
     racy: int = 0
     witness: Optional[Tuple[int, int, int, int]] = None
-    phase_counts: List[int] = field(default_factory=list)
+    phase_counts: Sequence[int] = field(default_factory=list)   # uint64 array for device results
     num_records: int = 0
 
     def key(self):
@@ -178,7 +178,7 @@ class Batch:
                 continue
             wit = (int(r["phase"]), int(r["index"]), int(r["tid_i"]), int(r["tid_j"])) if r["racy"] else None
             a = int(self.phase_off[i])
-            pc = [int(x) for x in counts[a:a + int(r["num_phases"])]]
+            pc = counts[a:a + int(r["num_phases"])]   # a view: no per-phase Python objects
             out.append(CheckResult(0, int(r["racy"]), wit, pc, int(r["num_records"])))
         return out
 

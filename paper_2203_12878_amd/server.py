@@ -104,6 +104,11 @@ class Server:
             self._cv.notify()
         return fut
 
+    def reset_stats(self):
+        """Start the statistics afresh (e.g. after a warm-up stream)."""
+        with self._cv:
+            self.stats = Stats()
+
     def close(self):
         with self._cv:
             self._stop = True
@@ -178,9 +183,11 @@ def run_stream(server: Server, requests: Sequence[Tuple[float, str, int]]):
     futs = []
     t0 = time.perf_counter()
     for at, code, n in coded:
+        # sleep only when the next arrival is well ahead (a short sleep
+        # overshoots by tens of microseconds); otherwise catch up at once
         delay = at - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
+        if delay > 2e-4:
+            time.sleep(delay - 1e-4)
         futs.append(server.submit(code, n))
     out = [f.result() for f in futs]
     return out, time.perf_counter() - t0
