@@ -494,6 +494,40 @@ DEV uint32_t cal_index(const uint32_t *__restrict__ ap, uint32_t tid, const uint
     return cal_chain(ap + CAL_HDR, rfl(ap[CAL_HDR - 1]), tid, U, ustride);
 }
 
+// A compiled access's header read once (uniform), for several iterations.
+struct CalHdr {
+    uint32_t mode, form, c0, m0k, m0, a, us, pk, pa, nops;
+    const uint32_t *ops;
+};
+DEV CalHdr cal_hdr(const uint32_t *__restrict__ ap) {
+    CalHdr h;
+    h.mode = rfl(ap[0]);
+    h.form = rfl(ap[1]);
+    h.c0 = rfl(ap[2]);
+    h.m0k = rfl(ap[3]);
+    h.m0 = rfl(ap[4]);
+    h.a = rfl(ap[5]);
+    h.us = rfl(ap[6]);
+    h.pk = rfl(ap[7]);
+    h.pa = rfl(ap[8]);
+    h.nops = rfl(ap[CAL_HDR - 1]);
+    h.ops = ap + CAL_HDR;
+    return h;
+}
+DEV uint32_t cal_eval(const CalHdr &h, uint32_t tid, const uint32_t *U, uint32_t ustride) {
+    if (h.form == 1u) {
+        uint32_t v = tid + h.c0;
+        if (h.m0k == CAL_K_AND) v &= h.m0;
+        else if (h.m0k == CAL_K_MOD) v = h.m0 ? v % h.m0 : v;
+        v *= h.a;
+        if (h.us != NONE32) v += rfl(U[h.us * ustride]);
+        if (h.pk == CAL_K_AND) v &= h.pa;
+        else if (h.pk == CAL_K_MOD) v = h.pa ? v % h.pa : v;
+        return v;
+    }
+    return cal_chain(h.ops, h.nops, tid, U, ustride);
+}
+
 struct CalLds {
     uint32_t u[CAL_U];
     uint32_t ph[CAL_CH];
@@ -544,29 +578,54 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
             }
         }
         __syncthreads();
-        for (uint32_t i = 0; i < ch; i++) {
-            const uint32_t pi = rfl(L.ph[i]);
-            const unsigned long long b = lds_base[pi];
-            const uint32_t lim = rfl(L.lim[i]);
-            if (b == ~0ull || it.tid0 >= lim) continue;
-            // a compiled leaf has no branches: the wave's active lanes are
-            // the same for every access of the iteration, so one
-            // reservation covers all of them (access j, lane l at
-            // r0 + j * na + rank of l)
-            const bool act = act0 && tid < lim;
-            const uint64_t m = ballot(act);
-            if (m == 0) continue;
-            const uint32_t na = (uint32_t)__builtin_popcountll(m);
-            uint32_t r0 = 0;
-            if (lane_id() == 0) r0 = atomicAdd(&lds_cur[pi], na * nacc);
-            const unsigned long long p0 = b + readlane(r0, 0) + mbcnt(m);
+        // EB iterations at a time: their reservations are issued together
+        // and each access header is read once for all of them
+        constexpr uint32_t EB = 4;
+        for (uint32_t i0 = 0; i0 < ch; i0 += EB) {
+            unsigned long long p0[EB];
+            uint32_t na[EB];
+            bool go[EB], act[EB];
+#pragma unroll
+            for (uint32_t q = 0; q < EB; q++) {
+                const uint32_t i = i0 + q;
+                go[q] = false;
+                act[q] = false;
+                na[q] = 0;
+                p0[q] = 0;
+                if (i >= ch) continue;
+                const uint32_t pi = rfl(L.ph[i]);
+                const unsigned long long b = lds_base[pi];
+                const uint32_t lim = rfl(L.lim[i]);
+                if (b == ~0ull || it.tid0 >= lim) continue;
+                // a compiled leaf has no branches: the wave's active lanes are
+                // the same for every access of the iteration, so one
+                // reservation covers all of them (access j, lane l at
+                // r0 + j * na + rank of l)
+                act[q] = act0 && tid < lim;
+                const uint64_t m = ballot(act[q]);
+                if (m == 0) continue;
+                go[q] = true;
+                na[q] = (uint32_t)__builtin_popcountll(m);
+                uint32_t r0 = 0;
+                if (lane_id() == 0) r0 = atomicAdd(&lds_cur[pi], na[q] * nacc);
+                p0[q] = b + readlane(r0, 0) + mbcnt(m);
+            }
+            bool any = false;
+#pragma unroll
+            for (uint32_t q = 0; q < EB; q++) any |= go[q];
+            if (!any) continue;
             const uint32_t *ap = acc0;
             for (uint32_t j = 0; j < nacc; j++) {
-                const uint32_t mode = rfl(ap[0]);
-                const uint32_t v = cal_index(ap, tid, L.u + i, chp);
-                const unsigned long long pos = p0 + (unsigned long long)j * na;
-                if (act && pos < cap) recs[pos] = ((unsigned long long)v << 32) | ((unsigned long long)tid << 1) | mode;
-                ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
+                const CalHdr h = cal_hdr(ap);
+#pragma unroll
+                for (uint32_t q = 0; q < EB; q++) {
+                    if (!go[q]) continue;
+                    const uint32_t v = cal_eval(h, tid, L.u + i0 + q, chp);
+                    const unsigned long long pos = p0[q] + (unsigned long long)j * na[q];
+                    if (act[q] && pos < cap)
+                        recs[pos] = ((unsigned long long)v << 32) | ((unsigned long long)tid << 1) | h.mode;
+                }
+                ap += CAL_HDR + 2 * h.nops;
             }
         }
         __syncthreads();
