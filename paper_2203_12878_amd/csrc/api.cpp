@@ -545,7 +545,7 @@ WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t ni
 // fit tiles in one level), at least 4 bits, at most the tuned maximum.
 uint32_t digit_bits_for(uint64_t len, uint32_t max_bits) {
     uint32_t b = 4;
-    while (b < max_bits && (len >> b) > 512) b++;
+    while (b < max_bits && (len >> b) > 1024) b++;
     return b;
 }
 
