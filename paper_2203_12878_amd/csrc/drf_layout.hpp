@@ -113,8 +113,9 @@ struct FixedVal {
     uint64_t value;
 };
 
-// Count / emit work item: one workgroup, lanes = tids tid0.., iterations
-// [f0, f1) of one nest; k_lo = global phase of f0, span = phases covered.
+// Count / emit work item: one workgroup, iterations [f0, f1) of one nest
+// for nblk consecutive blocks of 256 tids from tid0 (one block at a time,
+// lanes = tids); k_lo = global phase of f0, span = phases covered.
 struct Item {
     uint32_t nest;
     uint32_t tid0;
@@ -122,7 +123,7 @@ struct Item {
     uint64_t k_lo;
     uint64_t cnt_off;      // per-(item, phase) counts at cnt_off + (k - k_lo)
     uint32_t span;
-    uint32_t pad;
+    uint32_t nblk;         // blocks of 256 tids (>= 1)
 };
 
 // Fused work unit: phases [k0, k1) (global ids) of one protocol, each with

@@ -365,7 +365,8 @@ DEV void count_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, cons
         Odo<T> odo;
         odo.start(nd, it.f0 + q, vars);
         const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
-        const uint32_t na = lim > it.tid0 ? (lim - it.tid0 < (uint32_t)WG ? lim - it.tid0 : (uint32_t)WG) : 0u;
+        const uint32_t tids = it.nblk * (uint32_t)WG;   // the item's tids, all blocks
+        const uint32_t na = lim > it.tid0 ? (lim - it.tid0 < tids ? lim - it.tid0 : tids) : 0u;
         if (na) atomicAdd(&lds_cnt[odo.phase - it.k_lo], nacc * na);
     }
 }
@@ -394,28 +395,31 @@ __global__ __launch_bounds__(WG) void k_count(const Item *__restrict__ items, co
     if (compiled) {
         count_cal<T>(it, nd, pd, fixed, code, lds_cnt);
     } else {
-        T vars[MAXSLOTS];
-        for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
-        load_fixed<T>(nd, fixed, vars);
-        Odo<T> odo;
-        odo.start(nd, it.f0, vars);
-        const uint32_t tid = it.tid0 + threadIdx.x;
-        const bool act0 = tid < pd.n;
-        const uint32_t *leaf = code + nd.code_off;
         bool ovf = false;
-        CountSink sink{0};
-        uint64_t cur = odo.phase;
-        for (uint64_t f = it.f0; f < it.f1; f++) {
-            if (odo.phase != cur) {
-                if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
-                sink.n = 0;
-                cur = odo.phase;
+        for (uint32_t blk = 0; blk < it.nblk; blk++) {
+            const uint32_t tid0 = it.tid0 + blk * (uint32_t)WG;
+            T vars[MAXSLOTS];
+            for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+            load_fixed<T>(nd, fixed, vars);
+            Odo<T> odo;
+            odo.start(nd, it.f0, vars);
+            const uint32_t tid = tid0 + threadIdx.x;
+            const bool act0 = tid < pd.n;
+            const uint32_t *leaf = code + nd.code_off;
+            CountSink sink{0};
+            uint64_t cur = odo.phase;
+            for (uint64_t f = it.f0; f < it.f1; f++) {
+                if (odo.phase != cur) {
+                    if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
+                    sink.n = 0;
+                    cur = odo.phase;
+                }
+                // leaf loops never write for^S slots (binders are distinct)
+                if (tid0 < tid_limit<T>(nd, code, vars, pd.n)) run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+                odo.next(nd, vars);
             }
-            // leaf loops never write for^S slots (binders are distinct)
-            if (it.tid0 < tid_limit<T>(nd, code, vars, pd.n)) run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
-            odo.next(nd, vars);
+            if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
         }
-        if (lane_id() == 0 && sink.n) atomicAdd(&lds_cnt[cur - it.k_lo], sink.n);
         if (ballot(ovf) != 0 && lane_id() == 0) atomicOr(&proto_ovf[nd.proto], 1u);
     }
     __syncthreads();
@@ -554,8 +558,6 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
     const uint32_t nu = nuni ? nuni : 1u;
     static_assert(CAL_U / CAL_MAXU >= 64, "a chunk must hold one wave of iterations");
     const uint32_t chmax = (CAL_U / nu) / 64 * 64 < CAL_CH ? (CAL_U / nu) / 64 * 64 : CAL_CH;   // >= 64
-    const uint32_t tid = it.tid0 + threadIdx.x;
-    const bool act0 = tid < pd.n;
     for (uint64_t fc = it.f0; fc < it.f1; fc += chmax) {
         const uint32_t ch = (uint32_t)(it.f1 - fc < chmax ? it.f1 - fc : chmax);
         const uint32_t chp = (ch + 63) & ~63u;
@@ -578,54 +580,60 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
             }
         }
         __syncthreads();
-        // EB iterations at a time: their reservations are issued together
-        // and each access header is read once for all of them
+        // the item's tid blocks reuse the chunk's staging; EB iterations at
+        // a time: their reservations are issued together and each access
+        // header is read once for all of them
         constexpr uint32_t EB = 4;
-        for (uint32_t i0 = 0; i0 < ch; i0 += EB) {
-            unsigned long long p0[EB];
-            uint32_t na[EB];
-            bool go[EB], act[EB];
-#pragma unroll
-            for (uint32_t q = 0; q < EB; q++) {
-                const uint32_t i = i0 + q;
-                go[q] = false;
-                act[q] = false;
-                na[q] = 0;
-                p0[q] = 0;
-                if (i >= ch) continue;
-                const uint32_t pi = rfl(L.ph[i]);
-                const unsigned long long b = lds_base[pi];
-                const uint32_t lim = rfl(L.lim[i]);
-                if (b == ~0ull || it.tid0 >= lim) continue;
-                // a compiled leaf has no branches: the wave's active lanes are
-                // the same for every access of the iteration, so one
-                // reservation covers all of them (access j, lane l at
-                // r0 + j * na + rank of l)
-                act[q] = act0 && tid < lim;
-                const uint64_t m = ballot(act[q]);
-                if (m == 0) continue;
-                go[q] = true;
-                na[q] = (uint32_t)__builtin_popcountll(m);
-                uint32_t r0 = 0;
-                if (lane_id() == 0) r0 = atomicAdd(&lds_cur[pi], na[q] * nacc);
-                p0[q] = b + readlane(r0, 0) + mbcnt(m);
-            }
-            bool any = false;
-#pragma unroll
-            for (uint32_t q = 0; q < EB; q++) any |= go[q];
-            if (!any) continue;
-            const uint32_t *ap = acc0;
-            for (uint32_t j = 0; j < nacc; j++) {
-                const CalHdr h = cal_hdr(ap);
+        for (uint32_t blk = 0; blk < it.nblk; blk++) {
+            const uint32_t tid0 = it.tid0 + blk * (uint32_t)WG;
+            const uint32_t tid = tid0 + threadIdx.x;
+            const bool act0 = tid < pd.n;
+            for (uint32_t i0 = 0; i0 < ch; i0 += EB) {
+                unsigned long long p0[EB];
+                uint32_t na[EB];
+                bool go[EB], act[EB];
 #pragma unroll
                 for (uint32_t q = 0; q < EB; q++) {
-                    if (!go[q]) continue;
-                    const uint32_t v = cal_eval(h, tid, L.u + i0 + q, chp);
-                    const unsigned long long pos = p0[q] + (unsigned long long)j * na[q];
-                    if (act[q] && pos < cap)
-                        recs[pos] = ((unsigned long long)v << 32) | ((unsigned long long)tid << 1) | h.mode;
+                    const uint32_t i = i0 + q;
+                    go[q] = false;
+                    act[q] = false;
+                    na[q] = 0;
+                    p0[q] = 0;
+                    if (i >= ch) continue;
+                    const uint32_t pi = rfl(L.ph[i]);
+                    const unsigned long long b = lds_base[pi];
+                    const uint32_t lim = rfl(L.lim[i]);
+                    if (b == ~0ull || tid0 >= lim) continue;
+                    // a compiled leaf has no branches: the wave's active lanes are
+                    // the same for every access of the iteration, so one
+                    // reservation covers all of them (access j, lane l at
+                    // r0 + j * na + rank of l)
+                    act[q] = act0 && tid < lim;
+                    const uint64_t m = ballot(act[q]);
+                    if (m == 0) continue;
+                    go[q] = true;
+                    na[q] = (uint32_t)__builtin_popcountll(m);
+                    uint32_t r0 = 0;
+                    if (lane_id() == 0) r0 = atomicAdd(&lds_cur[pi], na[q] * nacc);
+                    p0[q] = b + readlane(r0, 0) + mbcnt(m);
                 }
-                ap += CAL_HDR + 2 * h.nops;
+                bool any = false;
+#pragma unroll
+                for (uint32_t q = 0; q < EB; q++) any |= go[q];
+                if (!any) continue;
+                const uint32_t *ap = acc0;
+                for (uint32_t j = 0; j < nacc; j++) {
+                    const CalHdr h = cal_hdr(ap);
+#pragma unroll
+                    for (uint32_t q = 0; q < EB; q++) {
+                        if (!go[q]) continue;
+                        const uint32_t v = cal_eval(h, tid, L.u + i0 + q, chp);
+                        const unsigned long long pos = p0[q] + (unsigned long long)j * na[q];
+                        if (act[q] && pos < cap)
+                            recs[pos] = ((unsigned long long)v << 32) | ((unsigned long long)tid << 1) | h.mode;
+                    }
+                    ap += CAL_HDR + 2 * h.nops;
+                }
             }
         }
         __syncthreads();
@@ -667,25 +675,28 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
         }
     }
 
-    T vars[MAXSLOTS];
-    for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
-    load_fixed<T>(nd, fixed, vars);
-    Odo<T> odo;
-    odo.start(nd, it.f0, vars);
-    const uint32_t tid = it.tid0 + threadIdx.x;
-    const bool act0 = tid < pd.n;
-    const uint32_t *leaf = code + nd.code_off;
-    bool ovf = false;
-    EmitSink sink{nullptr, 0, recs, cap, tid};
-    for (uint64_t f = it.f0; f < it.f1; f++) {
-        const uint32_t i = (uint32_t)(odo.phase - it.k_lo);
-        const unsigned long long b = lds_base[i];
-        if (b != ~0ull && it.tid0 < tid_limit<T>(nd, code, vars, pd.n)) {
-            sink.cur = &lds_cur[i];
-            sink.base = b;
-            run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+    for (uint32_t blk = 0; blk < it.nblk; blk++) {
+        const uint32_t tid0 = it.tid0 + blk * (uint32_t)WG;
+        T vars[MAXSLOTS];
+        for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+        load_fixed<T>(nd, fixed, vars);
+        Odo<T> odo;
+        odo.start(nd, it.f0, vars);
+        const uint32_t tid = tid0 + threadIdx.x;
+        const bool act0 = tid < pd.n;
+        const uint32_t *leaf = code + nd.code_off;
+        bool ovf = false;
+        EmitSink sink{nullptr, 0, recs, cap, tid};
+        for (uint64_t f = it.f0; f < it.f1; f++) {
+            const uint32_t i = (uint32_t)(odo.phase - it.k_lo);
+            const unsigned long long b = lds_base[i];
+            if (b != ~0ull && tid0 < tid_limit<T>(nd, code, vars, pd.n)) {
+                sink.cur = &lds_cur[i];
+                sink.base = b;
+                run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+            }
+            odo.next(nd, vars);
         }
-        odo.next(nd, vars);
     }
 }
 
