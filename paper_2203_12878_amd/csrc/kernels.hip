@@ -1636,7 +1636,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                             // are at most one tile)
                             const uint32_t L = lim < pd.n ? lim : pd.n;
                             const uint32_t R = L * nacc;
-                            const uint32_t M = L > 1 ? (uint32_t)(0xFFFFFFFFull / L) + 1u : 0u;
+                            const uint32_t M = L > 1 ? 0xFFFFFFFFu / L + 1u : 0u;
                             for (uint32_t e0 = 0; e0 < R; e0 += WG) {
                                 const uint32_t e = e0 + threadIdx.x;
                                 if (e < R) {
