@@ -130,3 +130,18 @@ def test_mixed_batch_subset(chk):
     _same([got[i] for i in small], want, [items[i] for i in small])
     for (t, n, lab), g in zip(batch, got):
         assert g.status == 0 and g.racy == (lab != "drf"), lab
+
+
+def test_decision_fallbacks(chk):
+    # one group whose survivors hold more distinct cells than the LDS hash
+    # table takes (each cell read twice by one thread): the survivors are
+    # sorted instead; then the same with a race at cell 3
+    items = [("(seq (rd (* tid 3)) (rd (* tid 3)))", 4096),
+             ("(seq (rd (* tid 3)) (rd (* tid 3)) (if (= tid 0) (wr 3) (skip)))", 4000),
+             # packed groups whose cells span more than 2^32 (phase above a
+             # 31-bit index): repeated cells are sorted without the hash table
+             ("(fors x 0 64 (seq (rd (* x 33554432)) (sync)))", 2),
+             ("(fors x 0 64 (seq (if (= tid 1) (wr (* x 33554432)) (rd (* x 33554432))) (sync)))", 2)]
+    got = chk.check_batch(items)
+    _same(got, o2.check_many(items, jobs=4), items)
+    assert [g.racy for g in got] == [0, 1, 0, 1]
