@@ -762,10 +762,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
             auto end = [&](uint32_t x) { return x + 1 < nd ? S[x + 1] : send; };
             // consecutive small buckets of one segment are contiguous and
             // hold disjoint index values: one tile takes the longest run of
-            // them that fits.  When one bucket spans few enough index values
-            // for the tile kernel's singleton filter, a tile stays within
-            // that span.
-            const uint32_t span = sg.shift < FILTER_BITS ? 1u << (FILTER_BITS - sg.shift) : nd;
+            // them that fits (a tile wider than the direct filter bitmap
+            // hashes its cells into it; fuller tiles are fewer)
             uint32_t d = 0;
             while (d < nd) {
                 const uint64_t a0 = S[d], len = end(d) - a0;
@@ -789,8 +787,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
                     d++;
                     continue;
                 }
-                // largest x in [d, d + span) with end(x) - a0 <= tile (ends are nondecreasing)
-                uint32_t lo = d, hi = std::min<uint32_t>(nd - 1, d + span - 1);
+                // largest x in [d, nd) with end(x) - a0 <= tile (ends are nondecreasing)
+                uint32_t lo = d, hi = nd - 1;
                 const uint64_t lim = a0 + tile;
                 while (lo < hi) {
                     const uint32_t m = (lo + hi + 1) >> 1;

@@ -13,7 +13,7 @@ constexpr int TILE = 8192;         // access events one LDS tile holds (64 KiB)
 constexpr int FUSED_PACK = 8192;   // events of a fused group of several phases
 constexpr int CHUNK = 4096;        // records per partition chunk (one workgroup)
 constexpr int RADIX = 1024;        // largest partition digit: 10 bits (starts stride per segment)
-constexpr uint32_t FILTER_BITS = 18; // tiles spanning at most 2^18 index values can drop singleton indices
+constexpr uint32_t FILTER_BITS = 18; // singleton filter bitmap bits (direct below 2^18 cells of span, else hashed)
 
 // Big-phase segment being partitioned by its next 8 (or fewer) index bits.
 struct Seg {
