@@ -1069,7 +1069,6 @@ static_assert(TILE / WG <= 32, "fused records per thread (one mask bit each)");
 static_assert(FUSED_PACK % WG == 0, "fused group size");
 constexpr uint32_t RED_WORDS = 5 * (TWG / 64) + 1;       // scan slots of the widest workgroup, then
 constexpr uint32_t RED_CAND = RED_WORDS - 1;             // the filter's repeat flag / hash cell counter
-constexpr uint32_t RED_PAIR = 36;                        // the witness pair (after the reductions)
 constexpr uint32_t RED_OVF = 38;                         // hash table overflow flag
 constexpr uint32_t RED_NC = 39;                          // survivor count
 // Up to SURV_CAP survivors of the filter are also kept compact in LDS,
@@ -1078,7 +1077,7 @@ constexpr uint32_t SURV_CAP = 1024;
 constexpr uint32_t SURV_WORDS = 2 * (SURV_CAP + SURV_CAP / 32);
 static_assert(SURV_WORDS <= FILTER_WORDS, "compact survivors overlap the repeated bitmap");
 static_assert((2 * TILE_LDS - SURV_WORDS) / 4 >= 2 * SURV_CAP, "no room for the table above the survivors");
-static_assert(RED_PAIR >= 4 * (TWG / 64) && RED_PAIR + 1 < RED_OVF && RED_NC < RED_CAND,
+static_assert(RED_OVF >= 4 * (TWG / 64) && RED_OVF < RED_NC && RED_NC < RED_CAND,
               "reduction slots overlap");
 
 // Exact decision of the filter's survivors by per-cell aggregation in an
@@ -1138,22 +1137,20 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
         if (tid != T0[h]) atomicMin(&T1[h], tid);
     });
     __syncthreads();
-    uint32_t bc = NONE32;
+    // least racy cell, with its slot in the low bits (a cell has one slot)
+    unsigned long long best = ~0ull, none = 0;
     for (uint32_t k = threadIdx.x; k < S; k += NT)
-        if (K[k] != NONE32 && T1[k] != NONE32 && W0[k] != NONE32 && K[k] < bc) bc = K[k];
-    bc = block_min(bc, red);
-    if (bc == NONE32) return 0;
-    for (uint32_t k = threadIdx.x; k < S; k += NT) {
-        if (K[k] == bc) {   // the cell's one slot
-            red[RED_PAIR] = T0[k];
-            red[RED_PAIR + 1] = W0[k] == T0[k] ? T1[k] : W0[k];
+        if (K[k] != NONE32 && T1[k] != NONE32 && W0[k] != NONE32) {
+            const unsigned long long c = ((unsigned long long)K[k] << 32) | k;
+            best = c < best ? c : best;
         }
-    }
-    __syncthreads();
-    key = lo + bc;
-    i1 = red[RED_PAIR];
-    i2 = red[RED_PAIR + 1];
-    __syncthreads();
+    block_minmax64(best, none, red);
+    if (best == ~0ull) return 0;
+    const uint32_t k = (uint32_t)best;
+    key = lo + (best >> 32);
+    i1 = T0[k];
+    i2 = W0[k] == T0[k] ? T1[k] : W0[k];
+    __syncthreads();   // the table is read before the caller reuses the LDS
     return 1;
 }
 
@@ -1245,10 +1242,12 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         return found;
     }
 
-    // filter: a seen bitmap first (most groups end there: no cell repeats),
-    // then a repeated bitmap, then the survivors: their mask per thread,
-    // and (up to SURV_CAP) a compact copy at a[ph(0..)], below the repeated
-    // bitmap (the seen bitmap is no longer read)
+    // filter: seen / repeated bitmaps (atomicOr returns the old word: a
+    // record whose cell was seen marks it repeated); when no cell repeats
+    // the group is race free (most groups end there), else the survivors:
+    // their mask per thread, and (up to SURV_CAP) a compact copy at
+    // a[ph(0..)], below the repeated bitmap (the seen bitmap is no longer
+    // read)
     uint32_t keepm = 0, nc;
     {
         const bool hashed = span > (1ull << FILTER_BITS);
@@ -1256,34 +1255,29 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         const uint32_t nw = hashed ? FILTER_WORDS : (((uint32_t)((span + 31) >> 5) + 3u) & ~3u);
         uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
         uint4 *seen4 = reinterpret_cast<uint4 *>(seen), *rep4 = reinterpret_cast<uint4 *>(rep);
-        for (uint32_t q = threadIdx.x; q < nw / 4; q += NT) seen4[q] = make_uint4(0u, 0u, 0u, 0u);
+        for (uint32_t q = threadIdx.x; q < nw / 4; q += NT) {
+            seen4[q] = make_uint4(0u, 0u, 0u, 0u);
+            rep4[q] = make_uint4(0u, 0u, 0u, 0u);
+        }
         if (threadIdx.x == 0) {
             red[RED_CAND] = 0;
             red[RED_NC] = 0;
         }
         __syncthreads();
-        // this thread's records whose cell was seen before
-        uint32_t repm = 0;
+        bool again = false;
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if ((uint32_t)j * NT + threadIdx.x < cnt) {
                 const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS), bit = 1u << (b & 31);
-                if (atomicOr(&seen[b >> 5], bit) & bit) repm |= 1u << j;
+                if (atomicOr(&seen[b >> 5], bit) & bit) {
+                    atomicOr(&rep[b >> 5], bit);
+                    again = true;
+                }
             }
         }
-        if (repm) red[RED_CAND] = 1;
+        if (again) red[RED_CAND] = 1;
         __syncthreads();
         if (red[RED_CAND] == 0) return false;   // every cell touched once
-        for (uint32_t q = threadIdx.x; q < nw / 4; q += NT) rep4[q] = make_uint4(0u, 0u, 0u, 0u);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((repm >> j) & 1u) {
-                const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
-                atomicOr(&rep[b >> 5], 1u << (b & 31));
-            }
-        }
-        __syncthreads();
 #pragma unroll
         for (int j = 0; j < E; j++) {
             const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
