@@ -194,8 +194,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-vs-plain and serving sections")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build checks protocols on one GPU; --gpus %d is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: the checker runs on one GPU; --gpus %d is not supported (there is no "
+              "multi-GPU path)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
