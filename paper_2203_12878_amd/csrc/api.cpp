@@ -836,12 +836,39 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         Best *best = at<Best>(A, C.o_best);
         Cand *cand = at<Cand>(A, C.o_cand);
         uint32_t *ovf = at<uint32_t>(A, C.o_ovf);
-        const ProtoDesc *dprotos = C.put(at<void>(A, C.o_protos), C.protos);
-        const NestDesc *dnests = C.put(at<void>(A, C.o_nests), C.nests);
-        const FixedVal *dfixed = C.put(at<void>(A, C.o_fixed), C.fixed);
-        const uint32_t *dcode = C.put(at<void>(A, C.o_code), C.code);
-        C.ditems[0] = C.put(at<void>(A, C.o_items[0]), C.items[0]);
-        C.ditems[1] = C.put(at<void>(A, C.o_items[1]), C.items[1]);
+        const ProtoDesc *dprotos;
+        const NestDesc *dnests;
+        const FixedVal *dfixed;
+        const uint32_t *dcode;
+        if (!rec) {
+            // the blob's parts are consecutive in pool A: one staged image,
+            // one copy
+            const size_t lo = C.o_protos, hi = C.o_items[1] + C.items[1].size() * sizeof(Item);
+            char *img = (char *)C.keep.take(hi - lo);
+            auto stage = [&](size_t off, const void *src, size_t bytes) {
+                if (bytes) memcpy(img + (off - lo), src, bytes);
+            };
+            stage(C.o_protos, C.protos.data(), C.protos.size() * sizeof(ProtoDesc));
+            stage(C.o_nests, C.nests.data(), C.nests.size() * sizeof(NestDesc));
+            stage(C.o_fixed, C.fixed.data(), C.fixed.size() * sizeof(FixedVal));
+            stage(C.o_code, C.code.data(), C.code.size() * sizeof(uint32_t));
+            stage(C.o_items[0], C.items[0].data(), C.items[0].size() * sizeof(Item));
+            stage(C.o_items[1], C.items[1].data(), C.items[1].size() * sizeof(Item));
+            if (hi > lo) hipck(hipMemcpyAsync(at<char>(A, lo), img, hi - lo, hipMemcpyHostToDevice, st));
+            dprotos = at<ProtoDesc>(A, C.o_protos);
+            dnests = at<NestDesc>(A, C.o_nests);
+            dfixed = at<FixedVal>(A, C.o_fixed);
+            dcode = at<uint32_t>(A, C.o_code);
+            C.ditems[0] = at<Item>(A, C.o_items[0]);
+            C.ditems[1] = at<Item>(A, C.o_items[1]);
+        } else {
+            dprotos = C.put(at<void>(A, C.o_protos), C.protos);
+            dnests = C.put(at<void>(A, C.o_nests), C.nests);
+            dfixed = C.put(at<void>(A, C.o_fixed), C.fixed);
+            dcode = C.put(at<void>(A, C.o_code), C.code);
+            C.ditems[0] = C.put(at<void>(A, C.o_items[0]), C.items[0]);
+            C.ditems[1] = C.put(at<void>(A, C.o_items[1]), C.items[1]);
+        }
         const Item *const *ditems = C.ditems;
         // the emit pass reads the blob through pool A offsets
         if (rec) {
