@@ -11,7 +11,7 @@ constexpr int WG = 256;            // lanes per workgroup of the evaluator kerne
 constexpr int MAXSPAN = 2048;      // phases one count / emit item may cover
 constexpr int TILE = 8192;         // access events one LDS tile holds (64 KiB)
 constexpr int FUSED_PACK = 8192;   // events of a fused group of several phases
-constexpr int CHUNK = 4096;        // records per partition chunk (one workgroup)
+constexpr int CHUNK = 8192;        // records per partition chunk (one workgroup)
 constexpr int RADIX = 1024;        // largest partition digit: 10 bits (starts stride per segment)
 constexpr uint32_t FILTER_BITS = 18; // singleton filter bitmap bits (direct below 2^18 cells of span, else hashed)
 
