@@ -462,10 +462,11 @@ struct Call {
             while (f1 - f0 > 1 && nest_phase(nd, f1 - 1) - k0 + 1 > (uint64_t)MAXSPAN) f1 = f0 + (f1 - f0) / 2;
             const uint32_t span = (uint32_t)(nest_phase(nd, f1 - 1) - k0 + 1);
             // several tid blocks per item when one block's share of the
-            // iterations holds few events (fewer items to build and launch)
+            // iterations holds few events (fewer items to build and launch;
+            // such an item may hold twice the events of a one-block item)
             const uint64_t blk_events = per_iter * (f1 - f0);
             const uint32_t per_item = (uint32_t)std::max<uint64_t>(
-                1, std::min<uint64_t>(ctx->tune.item_events / std::max<uint64_t>(1, blk_events), 64));
+                1, std::min<uint64_t>(2 * (uint64_t)ctx->tune.item_events / std::max<uint64_t>(1, blk_events), 64));
             for (uint32_t b = 0; b < nb; b += per_item) {
                 Item it{};
                 it.nest = ni;
