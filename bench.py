@@ -155,7 +155,7 @@ def serving(rates, requests_per_rate=5000):
     for rate in rates:
         horizon_s = min(1.0, requests_per_rate / rate)
         reqs = w.gen_requests(rate=float(rate), max_requests=int(rate * horizon_s * 2), horizon_s=horizon_s)
-        with Server(device=0, workers=2, budget_bytes=8 << 30) as srv:
+        with Server(device=0, workers=4, budget_bytes=8 << 30) as srv:
             # warm both workers (first launches, pinned staging) outside the figures
             run_stream(srv, [(0.0,) + tuple(q[1:]) for q in reqs[:16]])
             srv.reset_stats()
