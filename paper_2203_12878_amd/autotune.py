@@ -23,10 +23,10 @@ from . import drf
 SPACE = {
     "tile_events": [2048, 4096, 8192],
     "digit_bits": [6, 8, 10],
-    "unit_events": [4096, 16384, 65536, 262144],
+    "unit_events": [4096, 16384, 32768, 65536, 262144],
     "item_events": [1 << 14, 1 << 16, 1 << 18],
 }
-DEFAULT = {"tile_events": 8192, "digit_bits": 10, "unit_events": 1 << 16, "item_events": 1 << 16}
+DEFAULT = {"tile_events": 8192, "digit_bits": 10, "unit_events": 1 << 15, "item_events": 1 << 16}
 CACHE = os.environ.get("DRF_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "drf_tuning.json"))
 
 

@@ -63,7 +63,7 @@ struct drf_ctx {
     size_t h_counts_cap = 0;
     bool done_valid = false;
     uint32_t cus = 256;
-    drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 16, 1u << 16};
+    drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 15, 1u << 16};
     // per-kernel-class timing
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
