@@ -145,3 +145,15 @@ def test_decision_fallbacks(chk):
     got = chk.check_batch(items)
     _same(got, o2.check_many(items, jobs=4), items)
     assert [g.racy for g in got] == [0, 1, 0, 1]
+
+
+def test_multi_block_items(chk):
+    # leaves with a data-dependent branch (interpreted, not compiled) whose
+    # count / emit items span many 256-tid blocks, through the HBM path
+    # (phases of 65,536 records) and the fused path; racy and race free
+    items = [("(fors x 0 4 (seq (if (< (mod tid 3) 1) (wr tid) (rd (+ tid 1))) (sync)))", 65536),
+             ("(fors x 0 4 (seq (if (< (mod tid 3) 1) (wr (* tid 2)) (rd (+ (* tid 2) 1))) (sync)))", 65536),
+             ("(fors x 0 3 (seq (if (= (mod tid 7) 0) (wr (+ tid x)) (skip)) (sync)))", 3000)]
+    got = chk.check_batch(items)
+    _same(got, o2.check_many(items, jobs=4), items)
+    assert [g.racy for g in got] == [1, 0, 0]
