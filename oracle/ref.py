@@ -14,7 +14,7 @@ Liew, Cogumbreiro, Lange, PLACES 2022):
 * Thread-level control flow: Fig. "Syntax and semantics of BabyCUDA", rules
   seq, if-t, if-f, for-1, for-2 (half-open lo..hi, stride 1), skip; every
   thread runs independently (rule par) on T = {0..n-1}.
-* Synchronized fragment (left out of the paper "for presentation"): sync is a
+* Synchronized fragment (left out of the paper's presentation): sync is a
   barrier over all of T that closes the current phase and opens an empty one
   (histories are lists of phases, H ::= [] | P::H); phase k = the accesses
   performed after exactly k syncs.  for^S bounds are evaluated once and may
@@ -22,7 +22,7 @@ Liew, Cogumbreiro, Lange, PLACES 2022):
 * Race predicate: Definition 1 (DRF program): a phase is racy iff there are
   threads i1 != i2 and an index j with j written by i1 and read or written
   by i2; a history is DRF iff every phase is.  Access values i:o[j] and the
-  transport of a phase to a set of access values (Section 5, before
+  transport of a phase to a set of access values (Section 4, before
   Theorem 1) make a phase of a protocol the set of its access values.
 
 Outputs per protocol (all exact integers):

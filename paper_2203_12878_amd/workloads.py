@@ -268,7 +268,7 @@ def gen_requests(rate: float, max_requests: int = 20000, horizon_s: float = 10.0
 # ------------------------------------------------------- tiny enumeration
 _TINY_IDX_NOVAR = ["0", "1", "tid", "(+ tid 1)"]
 _TINY_IDX_VAR = ["x", "(+ tid x)", "(mod (+ tid x) 2)"]
-_TINY_GUARDS = ["true", "(= tid 0)", "(< tid 1)"]
+_TINY_GUARDS = ["true", "(= tid 0)", "(< tid 1)", "(<= tid 1)", "(!= tid 1)", "(> tid 1)", "false"]
 
 
 def _tiny_access(mode, idx, guard):
@@ -283,7 +283,8 @@ def enumerate_tiny(limit_random: int = 12000, seed: int = 0) -> Iterator[Tuple[s
 
     Exhaustive part: every sequence of up to two accesses and up to two
     syncs (any interleaving), each access drawn from modes {rd, wr}, indices
-    {0, 1, tid, tid+1} and guards {true, tid=0, tid<1}, optionally wrapped
+    {0, 1, tid, tid+1} and guards {true, tid=0, tid<1, tid<=1, tid!=1,
+    tid>1, false}, optionally wrapped
     whole in a fors or foru (when sync free) loop x in 0..b, b in {0,1,2}, in
     which case indices may also be x, tid+x, (tid+x) mod 2; thread counts
     n in {0,1,2,3}.  Random part: `limit_random` seeded draws with up to
@@ -351,7 +352,7 @@ def enumerate_tiny(limit_random: int = 12000, seed: int = 0) -> Iterator[Tuple[s
             else:
                 pool = _TINY_IDX_NOVAR + (_TINY_IDX_VAR if inside else [])
                 items.append(_tiny_access(modes[int(r.integers(0, 2))], pool[int(r.integers(0, len(pool)))],
-                                          _TINY_GUARDS[int(r.integers(0, 3))]))
+                                          _TINY_GUARDS[int(r.integers(0, len(_TINY_GUARDS)))]))
         if loop != "none":
             inner = items[lo_i:hi_i]
             inner_t = inner[0] if len(inner) == 1 else "(seq " + " ".join(inner) + ")"

@@ -134,6 +134,25 @@ def closed_form_cases():
         ("sync-free-fors", "(fors x 0 3 (wr (+ tid x)))", 2, 1, (0, 1, 0, 1), [6]),
         ("empty-phases", "(seq (sync) (sync) (wr tid))", 2, 0, None, [0, 0, 2]),
         ("seq-reuse", "(seq (fors x 0 2 (wr (+ (* 2 tid) x))) (fors x 0 2 (rd (+ (* 2 tid) x))))", 2, 0, None, [8]),
+        # relations at their boundary values: the guarded threads are the
+        # writers, so the verdict and the count name exactly which tids pass
+        ("le-two", "(if (<= tid 1) (wr 0) (skip))", 3, 1, (0, 0, 0, 1), [2]),        # tids 0, 1
+        ("le-one", "(if (<= tid 0) (wr 0) (skip))", 3, 0, None, [1]),                # tid 0 only
+        ("le-rev", "(if (<= 2 tid) (wr 6) (rd tid))", 4, 1, (0, 6, 2, 3), [4]),      # tids 2, 3 write
+        ("ne", "(if (!= tid 1) (wr 5) (skip))", 3, 1, (0, 5, 0, 2), [2]),            # tids 0, 2
+        ("ne-none", "(if (!= tid tid) (wr 5) (rd 5))", 3, 0, None, [3]),             # never true
+        ("gt", "(if (> tid 1) (wr 3) (skip))", 4, 1, (0, 3, 2, 3), [2]),             # tids 2, 3
+        ("gt-one", "(if (> tid 2) (wr 3) (rd 4))", 4, 0, None, [4]),                 # tid 3 alone writes
+        ("gt-rev", "(if (> 1 tid) (wr 3) (rd 3))", 3, 1, (0, 3, 0, 1), [3]),         # tid 0 writes, 1, 2 read
+        # the literal false
+        ("false", "(if false (wr 0) (rd 0))", 3, 0, None, [3]),
+        ("not-false", "(if (not false) (wr 0) (skip))", 2, 1, (0, 0, 0, 1), [2]),
+        ("or-false", "(if (or false (= tid 1)) (wr 4) (rd 4))", 3, 1, (0, 4, 0, 1), [3]),
+        ("and-false", "(if (and false true) (wr 4) (rd 4))", 3, 0, None, [3]),
+        # values just below the 2^63 limit through * and +: 2^62 mod 7 = 4,
+        # (2^63 - 8 + i) mod 5 = i mod 5
+        ("mul-below-limit", "(wr (mod (* tid 4611686018427387904) 7))", 2, 0, None, [2]),
+        ("add-below-limit", "(wr (mod (+ 9223372036854775800 tid) 5))", 8, 1, (0, 0, 0, 5), [8]),
     ]
     return cases
 
@@ -157,6 +176,9 @@ ERROR_CASES = [
     ("(fors x 0 9223372036854775808 (sync))", 0, ref.E_RANGE),     # for^S bounds checked once, even with no thread
     ("(if (or true (< (<< 1 100) 1)) (wr 0) (skip))", 1, ref.E_RANGE),  # both operands evaluated
     ("(if (< tid 1) (wr 0) (wr (* tid 4294967296)))", 1, 0),          # untaken branch is not evaluated
+    ("(wr (mod (* tid 4611686018427387904) 7))", 3, ref.E_RANGE),    # 2 * 2^62 reaches 2^63
+    ("(wr (mod (+ 9223372036854775800 tid) 5))", 9, ref.E_RANGE),    # 2^63 - 8 + 8
+    ("(if (< tid 2) (wr (mod (* tid 4611686018427387904) 7)) (skip))", 3, 0),   # guarded below the limit
     ("(wr 4294967295)", 1, 0),
     ("(wr (- 9223372036854775807 9223372036854775800))", 1, 0),
 ]
@@ -426,6 +448,49 @@ def _mut_reversed_phases(stmt, n):
     return list(reversed(_orig_expand(stmt, n)))
 
 
+_orig_apply_rel = ref.apply_rel
+
+
+def _mut_le_strict(op, a, b):
+    return a < b if op == "<=" else _orig_apply_rel(op, a, b)
+
+
+def _mut_ne_as_eq(op, a, b):
+    return a == b if op == "!=" else _orig_apply_rel(op, a, b)
+
+
+def _mut_gt_as_ge(op, a, b):
+    return a >= b if op == ">" else _orig_apply_rel(op, a, b)
+
+
+def _mut_swapped_operands(op, a, b):
+    return _orig_apply_rel(op, b, a) if op in ("<=", ">") else _orig_apply_rel(op, a, b)
+
+
+_orig_eval_b = ref.eval_b
+
+
+def _mut_false_true(c, env):
+    if c == "false":
+        return True
+    if isinstance(c, tuple) and c[0] in ("and", "or", "not"):
+        args = [_mut_false_true(x, env) for x in c[1:]]
+        return (not args[0]) if c[0] == "not" else (all(args) if c[0] == "and" else any(args))
+    return _orig_eval_b(c, env)
+
+
+def _mut_mul_wraps(op, a, b):
+    if op == "*":
+        return (a * b) % (1 << 64)            # no value-limit check
+    return _orig_apply_op(op, a, b)
+
+
+def _mut_add_unchecked(op, a, b):
+    if op == "+":
+        return a + b                          # no value-limit check
+    return _orig_apply_op(op, a, b)
+
+
 @pytest.mark.parametrize("target,mutant", [
     ("_pairwise_witness", _mut_same_thread),
     ("_pairwise_witness", _mut_read_read),
@@ -435,6 +500,13 @@ def _mut_reversed_phases(stmt, n):
     ("_run_u", _mut_inclusive_loop),
     ("expand", _mut_no_barrier),
     ("expand", _mut_reversed_phases),
+    ("apply_rel", _mut_le_strict),
+    ("apply_rel", _mut_ne_as_eq),
+    ("apply_rel", _mut_gt_as_ge),
+    ("apply_rel", _mut_swapped_operands),
+    ("eval_b", _mut_false_true),
+    ("apply_op", _mut_mul_wraps),
+    ("apply_op", _mut_add_unchecked),
 ])
 def test_planted_mistake_is_caught(monkeypatch, target, mutant):
     monkeypatch.setattr(ref, target, mutant)
