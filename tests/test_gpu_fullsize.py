@@ -1,0 +1,102 @@
+"""GPU parity at full size: the HIP path (through the C ABI) against oracle
+results stored by tests/golden/make_expected.py (which calls only the CPU
+oracle), on the full synthetic workloads:
+
+* the plain large protocol (65,536 threads, three nested for^S, 2^24
+  cells) for seeds whose protocol writes, through the plain and the
+  batched path;
+* the whole mixed batch (4096 protocols) and the whole tree-reduction
+  batch (2048 instances) in one batched check each;
+* a served Poisson stream at 5k req/s (1000 requests drawn 70/30 from the
+  mixed and tree generators), every request against its stored result.
+
+Every field is compared exactly: status, race flag, witness, record
+count, number of phases and the per-phase counts (in full when stored,
+else by their sha256 digest)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2203_12878_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _expected(name):
+    with open(os.path.join(GOLDEN, "expected_%s.json" % name)) as f:
+        return json.load(f)["results"]
+
+
+def _digest(counts):
+    c = counts.tolist() if hasattr(counts, "tolist") else list(counts)
+    return hashlib.sha256(" ".join(str(int(x)) for x in c).encode()).hexdigest()
+
+
+def _mismatches(got, exp):
+    assert len(got) == len(exp)
+    bad = []
+    for i, (g, e) in enumerate(zip(got, exp)):
+        same = (g.status, g.racy, list(g.witness) if g.witness else None, g.num_records) == \
+            (e["status"], e["racy"], e["witness"], e["num_records"])
+        if same and g.status == 0:
+            same = len(g.phase_counts) == e["num_phases"] and _digest(g.phase_counts) == e["phase_counts_sha256"]
+            if same and e["phase_counts"] is not None:
+                same = [int(x) for x in g.phase_counts] == e["phase_counts"]
+        if not same:
+            bad.append((i, g, e["status"], e["racy"], e["witness"], e["num_records"]))
+    return bad
+
+
+@pytest.fixture(scope="module")
+def chk():
+    from paper_2203_12878_amd import drf
+    c = drf.Checker(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_large_protocol_with_writes(chk, seed):
+    t, n = w.gen_large(seed)
+    exp = _expected("large%d" % seed)
+    assert "(wr " in t and exp[0]["num_records"] > 5 * 10 ** 7
+    print("large seed %d: %d events" % (seed, exp[0]["num_records"]), flush=True)
+    plain = chk.check(t, n)
+    assert _mismatches([plain], exp) == []
+    batched = chk.check_batch([(t, n)])
+    assert _mismatches(batched, exp) == []
+
+
+def test_mixed_batch_full(chk):
+    items = [(t, n) for t, n, _ in w.gen_mixed_batch(0, 4096)]
+    exp = _expected("mixed")
+    got = chk.check_batch(items)
+    bad = _mismatches(got, exp)
+    assert not bad, "%d of %d differ, first %r" % (len(bad), len(items), bad[:2])
+    assert sum(g.racy for g in got) == sum(e["racy"] for e in exp) > 0
+
+
+def test_tree_batch_full(chk):
+    items = [(t, n) for t, n, _ in w.gen_tree_batch(0, 2048)]
+    exp = _expected("tree")
+    got = chk.check_batch(items)
+    bad = _mismatches(got, exp)
+    assert not bad, "%d of %d differ, first %r" % (len(bad), len(items), bad[:2])
+
+
+def test_served_stream_matches_oracle():
+    from paper_2203_12878_amd.server import Server, run_stream
+    reqs = w.gen_requests(rate=5000.0, max_requests=1000, horizon_s=1.0)
+    exp = _expected("serve5k")
+    assert len(reqs) == len(exp) == 1000
+    with Server(device=0, workers=4, budget_bytes=8 << 30) as srv:
+        got, wall = run_stream(srv, reqs)
+        st = srv.stats
+    assert st.completed == len(reqs) and st.batches < len(reqs)
+    bad = _mismatches(got, exp)
+    assert not bad, "%d of %d differ, first %r" % (len(bad), len(reqs), bad[:2])
