@@ -1,18 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of data-race-freedom checking on one MI355X.
 
-One step = one full check (count, fused / partition / sort / scan passes,
-witness) of the workload's protocols through the C ABI, inputs already in
-host memory as compiled bytecode and outputs in device memory.  The default
-workload is the plain single large protocol: 65,536 threads, three nested
-for^S loops (bounds 1..32, product redrawn into [128, 508]), six affine-mod
-accesses into 2^24 cells (seed 0: 121,896,960 access events in 373 phases).
+One step = one full check (count, fused / partition / tile passes, witness)
+of the workload's protocols through the C ABI, inputs already in host
+memory as compiled bytecode and outputs in device memory.  The default
+workload is the batched configuration: 4096 seeded protocols (32..4096
+threads, loop depth 1..3, bounds 1..64, 2..8 accesses, 2^12..2^20 cells,
+about 20% racy by construction), 22.1 G access events, checked in one
+drf_check_batch call.
 
-Prints one JSON line.  Per-kernel times come from HIP events the library
-records around its own launches on its own stream while the timed steps
-run; the roofline entry is for the kernel class with the largest total
-time.  The CPU baseline is the C oracle run on the same protocol on the
-host (single thread: it checks one protocol at a time).
+Prints one JSON line:
+* the headline: records checked per second on the workload's path, with
+  parity against the stored oracle results;
+* `roofline`: the kernel class with the largest time, from HIP events the
+  library records around its own launches on its own stream;
+* `paths`: the batched path against the plain path (one drf_check_protocol
+  per protocol) on the whole mixed and tree-reduction batches, both with
+  parity;
+* `large`: the plain single large protocol (65,536 threads, 2^24 cells; a
+  seed whose protocol writes) with its tile-kernel roofline;
+* `serving`: Poisson streams of 1000 requests through the continuous-
+  batching server at 1k..50k req/s, p50/p99 latency, parity against the
+  stored oracle results and against each request checked alone;
+* `cpu_baseline`: the C oracle on a bounded sample of the workload, on one
+  host core and on all of them.
+
+`--calibrate-copy MiB` instead runs one plain device copy of that size (the
+reference for the HBM byte counters) and exits.
 """
 from __future__ import annotations
 
@@ -21,6 +35,7 @@ import ctypes
 import hashlib
 import json
 import os
+import platform
 import re
 import sys
 import time
@@ -29,50 +44,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
 # bytes per record the method must move with records materialized in HBM
 # (one 8-byte record write, its read-back by the conflict pass, and the
 # 8-byte histogram read of one partition level)
 EFFECTIVE_BYTES_PER_RECORD = 24
-# integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one 32-bit op per lane per clock)
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# the fused path writes each 8-byte record into LDS once and reads it back
+# once before deciding it
+FUSED_LDS_BYTES_PER_RECORD = 16
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
-def workload(name: str):
+def workload(name: str, seed: int):
     from paper_2203_12878_amd import workloads as w
     if name == "large":
-        t, n = w.gen_large(0)
-        return [(t, n)], "plain single large protocol, seed 0: 65536 threads, 3 nested for^S, 6 accesses, 2^24 cells"
+        t, n = w.gen_large(seed)
+        return [(t, n)], "large", ("plain single large protocol, seed %d: 65536 threads, 3 nested for^S "
+                                   "(bounds 1..32), 6 accesses, 2^24 cells" % seed)
     if name == "small":
         t, n = w.gen_small(0)
-        return [(t, n)], "plain single small protocol, seed 0: 256 threads, for^S 16 x 4, 4 accesses, 4096 cells"
+        return [(t, n)], "small", "plain single small protocol, seed 0: 256 threads, for^S 16 x 4, 4 accesses"
     if name == "mixed":
         b = w.gen_mixed_batch(0, 4096)
-        return [(t, n) for t, n, _ in b], "mixed batch, seed 0: 4096 protocols, 32..4096 threads, depth 1..3"
+        return [(t, n) for t, n, _ in b], "mixed", ("batched: 4096 seeded protocols (seed 0), 32..4096 threads, "
+                                                    "depth 1..3, bounds 1..64, 2..8 accesses, 2^12..2^20 cells")
     if name == "tree":
         b = w.gen_tree_batch(0, 2048)
-        return [(t, n) for t, n, _ in b], "tree-reduction batch, seed 0: 2048 instances, 2^8..2^20 threads"
+        return [(t, n) for t, n, _ in b], "tree", ("batched tree reductions: 2048 instances (seed 0), "
+                                                   "2^8..2^20 threads, one level's sync removed in half")
     raise SystemExit("unknown workload " + name)
 
 
-def expr_ops(text: str) -> int:
-    """Arithmetic operators in the access index expressions (per event)."""
-    ops = 0
-    accs = 0
-    for m in re.finditer(r"\((rd|wr) ", text):
-        depth, i = 0, m.end()
-        j = i
-        while j < len(text):
-            c = text[j]
-            if c == "(":
-                depth += 1
-            elif c == ")":
-                if depth == 0:
-                    break
-                depth -= 1
-            j += 1
-        ops += len(re.findall(r"\((?:\+|-|\*|/|mod|<<|>>|min|max) ", text[i:j]))
-        accs += 1
-    return max(1, round(ops / max(1, accs)))
+def golden_name(name: str, seed: int) -> str:
+    return "large%d" % seed if name == "large" and seed else name
 
 
 class KStat(ctypes.Structure):
@@ -91,7 +96,6 @@ def kernel_stats(lib, ctx, reset=True):
 
 
 def kernels_sha256() -> str:
-    import hashlib
     h = hashlib.sha256()
     for f in ("kernels.hip", "kernels.hpp", "drf_layout.hpp"):
         with open(os.path.join(ROOT, "paper_2203_12878_amd", "csrc", f), "rb") as fh:
@@ -99,11 +103,11 @@ def kernels_sha256() -> str:
     return h.hexdigest()
 
 
-def committed_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
+def committed_traffic(kernel: str, wl: str):
+    """HBM bytes per launch of `kernel` on workload `wl` from the committed
     rocprofv3 counter summary, or None when none exists or the kernels have
     changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload))
+    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, wl))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -120,146 +124,228 @@ def committed_traffic(kernel: str, workload: str):
         return None
 
 
-def compare_paths(drf, chk):
-    """Batched (one check over the whole set) against plain (one protocol
-    per call) on a sample of the batched workloads."""
+def counts_sha(c) -> str:
+    """The stored digest: sha256 of the per-phase counts in decimal, space separated."""
+    c = c.tolist() if hasattr(c, "tolist") else list(c)
+    return hashlib.sha256(" ".join(str(int(x)) for x in c).encode()).hexdigest()
+
+
+def parity(results, gname: str):
+    """Every field of every result against the stored oracle results (None
+    when none are stored for this workload)."""
+    path = os.path.join(GOLDEN, "expected_%s.json" % gname)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        exp = json.load(f)["results"]
+    return len(exp) == len(results) and all(
+        [r.status, r.racy, list(r.witness) if r.witness else None, r.num_records] ==
+        [e["status"], e["racy"], e["witness"], e["num_records"]] and
+        (r.status != 0 or (len(r.phase_counts) == e["num_phases"] and counts_sha(r.phase_counts) ==
+                           e["phase_counts_sha256"])) for r, e in zip(results, exp))
+
+
+def timed(run, batch, steps, warmup, lib=None, ctx=None):
+    """Warm-up runs, then `steps` timed runs bracketed by device syncs.
+    Returns (seconds per step, per-kernel stats of the timed runs)."""
     import torch
-    from paper_2203_12878_amd import workloads as w
-    items = [(t, n) for t, n, _ in w.gen_mixed_batch(0, 512)] + [(t, n) for t, n, _ in w.gen_tree_batch(0, 128)]
+    for _ in range(warmup):
+        run(batch)
+    torch.cuda.synchronize()
+    if lib is not None:
+        lib.drf_ctx_set_profiling(ctx, 1)
+        kernel_stats(lib, ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run(batch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = None
+    if lib is not None:
+        lib.drf_ctx_set_profiling(ctx, 0)
+        stats = kernel_stats(lib, ctx, reset=True)
+    return (t1 - t0) / steps, stats
+
+
+def roofline(stats, steps, records, wl):
+    """Roofline entry of the kernel class with the largest time."""
+    dname, d = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    launches = max(1, d["launches"])
+    avg_ms = d["ms"] / launches
+    if dname == "fused":
+        # the fused path keeps records in LDS: its records are those not
+        # emitted to HBM; bound against the LDS bandwidth
+        emitted = stats.get("emit", {}).get("records", 0) // max(1, steps)
+        recs = (records - emitted) * steps
+        achieved = recs * FUSED_LDS_BYTES_PER_RECORD / (d["ms"] / 1e3) / 1e9
+        return {"kernel": dname, "bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
+                "traffic": committed_traffic(dname, wl), "records_per_launch": recs // launches,
+                "lds_bytes_per_record": FUSED_LDS_BYTES_PER_RECORD, "avg_launch_ms": round(avg_ms, 4)}
+    achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9
+    return {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(dname, wl),
+            "bytes_per_launch": d["bytes"] // launches, "avg_launch_ms": round(avg_ms, 4)}
+
+
+def per_kernel(stats, steps):
+    return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": v["launches"] // steps,
+                "records_per_step": v["records"] // steps, "bytes_per_step": v["bytes"] // steps}
+            for k, v in stats.items() if v["launches"]}
+
+
+def compare_paths(drf, chk, name, steps):
+    """Batched (one check over the whole set) against plain (one protocol
+    per call) on a whole batched workload, both compared with the oracle."""
+    items, wl, _ = workload(name, 0)
     batch = drf.Batch(items, 0)
     out = {}
-    for name, run in (("batched", chk.run_batch), ("plain", chk.run_plain)):
-        run(batch)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = 2
-        for _ in range(reps):
-            run(batch)
-        torch.cuda.synchronize()
-        out[name] = (time.perf_counter() - t0) / reps
+    for path, run, k in (("batched", chk.run_batch, steps), ("plain", chk.run_plain, 1)):
+        secs, _ = timed(run, batch, k, 1)
+        res = batch.collect()
+        out[path] = (secs, parity(res, wl))
     recs = sum(r.num_records for r in batch.collect())
-    return {"sample": "first 512 protocols of the mixed batch and first 128 tree instances (seed 0), %d records" % recs,
-            "batched_records_per_s": round(recs / out["batched"], 1), "plain_records_per_s": round(recs / out["plain"], 1),
-            "batched_ms": round(out["batched"] * 1e3, 3), "plain_ms": round(out["plain"] * 1e3, 3),
-            "speedup": round(out["plain"] / out["batched"], 3)}
+    return {"protocols": len(items), "records": recs,
+            "batched_records_per_s": round(recs / out["batched"][0], 1),
+            "plain_records_per_s": round(recs / out["plain"][0], 1),
+            "batched_ms": round(out["batched"][0] * 1e3, 3), "plain_ms": round(out["plain"][0] * 1e3, 3),
+            "speedup": round(out["plain"][0] / out["batched"][0], 3),
+            "parity_batched": out["batched"][1], "parity_plain": out["plain"][1]}
 
 
-def serving(rates, requests_per_rate=5000):
-    """Poisson streams of check requests through the continuous-batching
-    server: latency percentiles and throughput per offered rate.  Each
-    stream lasts about requests_per_rate / rate seconds (one second at
-    most)."""
+def serving(drf, rates):
+    """Poisson streams of 1000 requests (70/30 mixed / tree generators)
+    through the server: latency percentiles, throughput, and parity of every
+    result against the stored oracle results and against the request
+    checked alone."""
     from paper_2203_12878_amd import workloads as w
     from paper_2203_12878_amd.server import Server, run_stream
     rows = []
+    alone_chk = drf.Checker(0)
     for rate in rates:
-        horizon_s = min(1.0, requests_per_rate / rate)
-        reqs = w.gen_requests(rate=float(rate), max_requests=int(rate * horizon_s * 2), horizon_s=horizon_s)
+        reqs = w.gen_requests(rate=float(rate), max_requests=1000, horizon_s=1.0)
         with Server(device=0, workers=4, budget_bytes=8 << 30) as srv:
-            # warm both workers (first launches, pinned staging) outside the figures
+            # warm the workers (first launches, pinned staging) outside the figures
             run_stream(srv, [(0.0,) + tuple(q[1:]) for q in reqs[:16]])
             srv.reset_stats()
             res, wall = run_stream(srv, reqs)
             st = srv.stats
+        b = drf.Batch([(t, n) for _, t, n, _ in reqs], 0)
+        alone_chk.run_plain(b)
+        import torch
+        torch.cuda.synchronize()
+        alone = b.collect()
         recs = sum(r.num_records for r in res)
         rows.append({"offered_req_per_s": rate, "requests": len(reqs), "p50_ms": round(st.percentile(50) * 1e3, 3),
                      "p99_ms": round(st.percentile(99) * 1e3, 3), "records_per_s": round(recs / wall, 1),
-                     "req_per_s": round(len(reqs) / wall, 1), "batches": st.batches})
+                     "req_per_s": round(len(reqs) / wall, 1), "batches": st.batches,
+                     "max_in_flight_bytes": st.max_in_flight_bytes,
+                     "parity_vs_oracle": parity(res, "serve%dk" % (rate // 1000)),
+                     "parity_vs_alone": all(a.key() == m.key() for a, m in zip(alone, res))})
+    alone_chk.close()
     return rows
 
 
-def cpu_baseline(items, records_per_step):
-    """The C oracle on the same protocols, on host cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(items, records_target=2.0e8):
+    """The C oracle on a bounded sample of the workload: the protocols in
+    order until their planned events reach records_target, on one host
+    thread and on all of the host's threads (up to 16)."""
     from oracle import o2
-    t0 = time.perf_counter()
-    res, secs = o2.check_many(items, jobs=1, timing=True)
-    recs = sum(r.num_records for r in res)
-    return {"value": recs / secs, "unit": "records/s", "cores": 1, "kind": "oracle",
-            "sample": "the whole workload (%d protocol(s), %d access events) through the C oracle, one thread, %.1f s"
-                      % (len(items), recs, secs)}, res
+    from paper_2203_12878_amd import drf
+    sample, est = [], 0
+    for t, n in items:
+        p = drf.plan(t, n)
+        if sample and est + p.max_records > records_target:
+            continue
+        sample.append((t, n))
+        est += p.max_records
+        if est >= records_target:
+            break
+    nproc = os.cpu_count() or 1
+    jobs = max(1, min(16, nproc, len(sample)))
+    res1, s1 = o2.check_many(sample, jobs=1, timing=True)
+    resn, sn = o2.check_many(sample, jobs=jobs, timing=True)
+    recs = sum(r.num_records for r in res1)
+    assert [r.key() for r in res1] == [r.key() for r in resn]
+    what = "%d protocol(s) of the workload in generator order, %d access events" % (len(sample), recs)
+    return {"value": round(recs / sn, 1), "unit": "records/s", "cores": jobs, "kind": "oracle",
+            "sample": what + "; %d threads %.1f s" % (jobs, sn),
+            "single_core": {"value": round(recs / s1, 1), "cores": 1, "seconds": round(s1, 2)},
+            "nproc": nproc, "cpu_model": cpu_model()}
+
+
+def calibrate_copy(mib: int):
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n, "read": n, "write": n}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "mixed", "tree"])
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "tree", "large", "small"])
+    ap.add_argument("--seed", type=int, default=1, help="seed of the large protocol (1: one that writes)")
     ap.add_argument("--path", default="auto", choices=["auto", "plain", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile-events", type=int, default=0, help="tuning override (0: library default)")
+    ap.add_argument("--no-extras", action="store_true", help="headline only (no paths / large / serving)")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner for this workload first (cached)")
+    ap.add_argument("--no-tuning-cache", action="store_true", help="library default tuning")
+    ap.add_argument("--tuning-cache", default=None, help="tuning cache file (default: the package's)")
+    ap.add_argument("--tile-events", type=int, default=0, help="tuning override (0: cached or default)")
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--unit-events", type=int, default=0)
     ap.add_argument("--item-events", type=int, default=0)
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched-vs-plain and serving sections")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the checker runs on one GPU; --gpus %d is not supported (there is no "
               "multi-GPU path)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
-    import torch
-    from paper_2203_12878_amd import drf
+    from paper_2203_12878_amd import autotune, drf
 
-    items, desc = workload(args.workload)
+    items, wl, desc = workload(args.workload, args.seed)
+    gname = golden_name(args.workload, args.seed)
     path = args.path if args.path != "auto" else ("plain" if len(items) == 1 else "batch")
     chk = drf.Checker(0)
+    lib = drf.lib()
+    batch = drf.Batch(items, 0)
+    tuning_source = "library default"
+    cache = args.tuning_cache or autotune.CACHE
+    if args.tune:
+        autotune.tune(chk, batch, cache_path=cache, verbose=True)
+        tuning_source = "autotuned now"
+    elif not args.no_tuning_cache and autotune.apply_cached(chk, batch, cache_path=cache):
+        tuning_source = "autotuner cache (%s)" % autotune.size_class(batch)
     chk.set_tuning(tile_events=args.tile_events, digit_bits=args.digit_bits, unit_events=args.unit_events,
                    item_events=args.item_events)
-    lib = drf.lib()
-    lib.drf_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    batch = drf.Batch(items, 0)
     run = chk.run_plain if path == "plain" else chk.run_batch
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        run(batch)
-    stream.synchronize()
-    lib.drf_ctx_set_profiling(chk._ctx, 1)
-    kernel_stats(lib, chk._ctx, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run(batch)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lib.drf_ctx_set_profiling(chk._ctx, 0)
-    stats = kernel_stats(lib, chk._ctx, reset=True)
+    secs, stats = timed(run, batch, args.steps, args.warmup, lib, chk._ctx)
     results = batch.collect()
     records = sum(r.num_records for r in results)
-    racy = sum(r.racy for r in results)
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    value = records / ((t1 - t0) / args.steps)
-
-    # parity of this run against stored oracle results (when present)
-    parity = None
-    gold = os.path.join(ROOT, "tests", "golden", "expected_%s.json" % args.workload)
-    if os.path.exists(gold):
-        with open(gold) as f:
-            exp = json.load(f)["results"]
-        def counts_sha(c):   # the stored digest: sha256 of the counts in decimal, space separated
-            c = c.tolist() if hasattr(c, "tolist") else list(c)
-            return hashlib.sha256(" ".join(str(x) for x in c).encode()).hexdigest()
-        parity = len(exp) == len(results) and all(
-            [r.status, r.racy, list(r.witness) if r.witness else None, r.num_records] ==
-            [e["status"], e["racy"], e["witness"], e["num_records"]] and
-            (r.status != 0 or counts_sha(r.phase_counts) == e["phase_counts_sha256"]) for r, e in zip(results, exp))
-
-    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
-    dname, d = dom
-    launches = max(1, d["launches"])
-    avg_ms = d["ms"] / launches
-    if d["bytes"] > 0:
-        achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9
-        roof = {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": committed_traffic(dname, args.workload),
-                "bytes_per_launch": d["bytes"] // launches, "avg_launch_ms": round(avg_ms, 4)}
-    else:
-        ops = expr_ops(items[0][0]) if len(items) == 1 else 1
-        achieved = d["records"] * ops / (d["ms"] / 1e3) / 1e12
-        roof = {"kernel": dname, "bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TOPS,
-                "unit": "Tops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
-                "ops_per_record": ops, "avg_launch_ms": round(avg_ms, 4)}
+    value = records / secs
 
     line = {
         "metric": "access records checked/s",
@@ -268,29 +354,40 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(secs * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "path": path, "protocols": len(items),
-                   "records_per_step": records, "racy_protocols": racy, "tuning": chk.tuning()},
-        "parity_vs_stored_oracle": parity,
-        "roofline": roof,
+        "config": {"workload": desc, "name": wl, "path": "batched" if path == "batch" else "plain",
+                   "protocols": len(items), "records_per_step": records,
+                   "racy_protocols": sum(r.racy for r in results),
+                   "tuning": dict(chk.tuning(), source=tuning_source)},
+        "parity_vs_stored_oracle": parity(results, gname),
+        "roofline": roofline(stats, args.steps, records, wl),
         "effective_hbm_frac": round(value * EFFECTIVE_BYTES_PER_RECORD / (HBM_PEAK_GBS * 1e9), 4),
-        "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4), "launches_per_step": v["launches"] // args.steps,
-                        "records_per_step": v["records"] // args.steps, "bytes_per_step": v["bytes"] // args.steps}
-                    for k, v in stats.items() if v["launches"]},
+        "kernels": per_kernel(stats, args.steps),
     }
-    if not args.no_cpu_baseline:
-        cb, _ = cpu_baseline(items if len(items) == 1 else items[:64], records)
-        line["cpu_baseline"] = cb
     if not args.no_extras:
-        line["batched_vs_plain"] = compare_paths(drf, chk)
-        line["serving"] = serving([1000, 5000, 20000, 50000])
-    print(json.dumps(line), flush=True)
+        line["paths"] = {n: compare_paths(drf, chk, n, args.steps) for n in ("mixed", "tree")}
+        litems, _, ldesc = workload("large", args.seed)
+        lb = drf.Batch(litems, 0)
+        lsecs, lstats = timed(chk.run_plain, lb, max(3, args.steps), 1, lib, chk._ctx)
+        lres = lb.collect()
+        lrec = sum(r.num_records for r in lres)
+        line["large"] = {"workload": ldesc, "path": "plain", "records_per_s": round(lrec / lsecs, 1),
+                         "ms_per_step": round(lsecs * 1e3, 3), "records_per_step": lrec,
+                         "racy": lres[0].racy, "parity_vs_stored_oracle": parity(lres, golden_name("large", args.seed)),
+                         "roofline": roofline(lstats, max(3, args.steps), lrec, "large"),
+                         "effective_hbm_frac": round(lrec / lsecs * EFFECTIVE_BYTES_PER_RECORD /
+                                                     (HBM_PEAK_GBS * 1e9), 4),
+                         "kernels": per_kernel(lstats, max(3, args.steps))}
+        line["serving"] = serving(drf, [1000, 5000, 20000, 50000])
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(items)
     chk.close()
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

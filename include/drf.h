@@ -34,7 +34,7 @@
  * words, statements in prefix order:
  *   header      'MAP1' (0x3150414D), version (1), num_slots, code_words
  *   SKIP  0x01
- *   ACC   0x02 mode(0 rd, 1 wr) <expr>
+ *   ACC   0x02 mode(0 rd, 1 wr; | array << 1) <expr>
  *   SEQ   0x03 count <stmt>*count
  *   IF    0x04 <cond> <stmt then> <stmt else>
  *   FORU  0x05 slot <expr lo> <expr hi> <stmt body>
@@ -62,6 +62,7 @@
  *   DRF_E_SYNC_IN_U  sync or for^S under if or for^U
  *   DRF_E_DIVERGENT  for^S bounds mention tid
  *   DRF_E_RANGE      an evaluated value >= 2^63 or index >= 2^32
+ *   DRF_E_MULTI      the protocol accesses several arrays (drf_check_arrays)
  *   DRF_E_LIMIT      outside this implementation's limits (more than 16
  *                    loop slots, more than 8 nested for^S, expression stack
  *                    deeper than 16, if/for^U nesting deeper than 30,
@@ -71,14 +72,30 @@
  * are 0xFFFFFFFF.  Nothing throws or aborts across this ABI.
  *
  * Memory and streams.  Device pointers (prefix d_) are caller-owned device
- * memory; host pointers (h_ or none) are read during the call only.  The
- * context owns a device scratch pool that grows on demand up to the limit
- * given at creation and is reused across calls; it never holds caller
- * memory.  A context is used by one host thread at a time; use one context
- * per thread (and stream) for concurrent checking.  The checking calls
- * enqueue work on `stream` (a hipStream_t) and return once the work is
- * enqueued; they wait on the stream internally once, after counting, to
- * size the rest.  Results are valid after the caller synchronizes `stream`.
+ * memory; host pointers (h_ or none) are read during the call only (the
+ * caller may free them on return).  Device scratch is not caller-owned:
+ * each context keeps two scratch pools that grow on demand in stream order
+ * (hipMallocAsync on the call's stream), never beyond the limit given at
+ * creation (DRF_E_NOMEM when a call cannot fit even after splitting its
+ * big phases into waves), are reused across calls and can be handed back
+ * with drf_ctx_release.  The sizes come from the per-phase counts that the
+ * count pass finds on the device, which a caller cannot know in advance;
+ * drf_plan.scratch_bytes gives an upper bound for admission control.  A
+ * context is used by one host thread at a time; use one context per thread
+ * (and stream) for concurrent checking.
+ *
+ * Asynchrony.  The checking calls enqueue their work on `stream` (a
+ * hipStream_t; NULL = the default stream) and return without waiting for
+ * its completion: results and counts are valid after the caller
+ * synchronizes `stream`.  The host does wait inside a call where it needs
+ * device data to plan further work: once for the per-phase counts of the
+ * protocols whose phases the planner cannot prove small (statically small
+ * protocols need no wait at all), once per partition level of phases
+ * above one tile (the host packs the next tiles from the bucket starts
+ * while the scatter runs), and, at the start of a call, for the same
+ * context's previous call (its pinned staging is reused).  `stream` must be
+ * a live stream of the context's device (HIP does not validate handles: a
+ * stale or made-up one is undefined behaviour, as in HIP itself).
  */
 #ifndef DRF_H
 #define DRF_H
@@ -101,6 +118,8 @@ extern "C" {
 #define DRF_E_NOMEM (-8)
 #define DRF_E_HIP (-9)
 #define DRF_E_LIMIT (-10)
+#define DRF_E_MULTI (-11)
+#define DRF_E_ILLTYPED (-12)
 
 #define DRF_MAGIC 0x3150414Du
 #define DRF_TID_SLOT 0xFFFFFFFFu
@@ -117,7 +136,10 @@ typedef struct {
     uint64_t max_records;  /* upper bound on executed access events */
     uint64_t nests;        /* unsynchronized leaves times host-unrolled iterations */
     uint64_t max_phase_records;  /* upper bound on the events of any one phase */
-} drf_plan;                /* 40 bytes */
+    uint64_t scratch_bytes;      /* upper bound on the device scratch a check of this
+                                    protocol alone takes (a limit below it splits the
+                                    big phases into waves; see drf_ctx_create) */
+} drf_plan;                /* 48 bytes */
 
 /* Result of one protocol. */
 typedef struct {
@@ -130,6 +152,8 @@ typedef struct {
 } drf_result;              /* 40 bytes */
 
 /* Compile the s-expression text form of one protocol into bytecode.
+ * Defines: the MAP syntax (Section 2, Fig. "Syntax of MAPs"), with the
+ * operators and relations of the index language spelled out above.
  * text/len: the text (need not be NUL terminated).  out/cap: output words.
  * *nwords receives the number of words written (or needed, when cap is too
  * small: then DRF_E_NOMEM).  DRF_E_ARG for text that is not a protocol.
@@ -138,32 +162,146 @@ typedef struct {
 int drf_compile_text(const char *text, size_t len, uint32_t *out, uint32_t cap, uint32_t *nwords);
 
 /* Validate and plan one protocol run by num_threads threads (host only).
- * code/words: bytecode.  Writes *out; returns DRF_OK unless arguments are
- * invalid (the protocol's own problems go in out->status). */
+ * Defines: the well-formedness side conditions of the typing rules
+ * (Section 4, Fig. "Behavioral type system": variables in scope for rules
+ * t-n / t-b, distinct binders) and the split of a synchronized protocol
+ * into barrier-separated phases (Section 2, synchronized protocols).
+ * code/words: bytecode.  Writes *out (scratch_bytes for the default
+ * tuning); returns DRF_OK unless arguments are invalid (the protocol's own
+ * problems go in out->status). */
 int drf_plan_protocol(const uint32_t *code, uint32_t words, uint32_t num_threads, drf_plan *out);
 
-/* Create a context on HIP device `hip_device`; scratch_limit_bytes bounds
- * the device scratch pool (0 = 3/4 of the free device memory). */
-int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out);
-int drf_ctx_destroy(drf_ctx *ctx);
+/* Plan `count` protocols laid out as for drf_check_batch (host only).
+ * plans: count drf_plan (host), each as drf_plan_protocol gives it.
+ * *scratch_bytes_total (may be NULL): upper bound on the device scratch
+ * one drf_check_batch of all of them takes.  ctx (may be NULL) supplies
+ * the tuning the sizes are computed for (the library default when NULL);
+ * it is only read.  DRF_E_ARG for missing arrays. */
+int drf_plan_batch(const drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                   uint32_t count, drf_plan *plans, uint64_t *scratch_bytes_total);
 
-/* Check one protocol.  d_result: one drf_result in device memory.
- * d_phase_counts: device array of phase_cap u64 (needs plan.num_phases).
- * stream: hipStream_t (NULL = default stream). */
+/* Create a context on HIP device `hip_device`; scratch_limit_bytes bounds
+ * the two device scratch pools together (0 = 3/4 of the free device
+ * memory).  DRF_E_HIP when the device does not exist or HIP fails. */
+int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out);
+/* Waits for the context's work, frees its pools and staging. */
+int drf_ctx_destroy(drf_ctx *ctx);
+/* Hands the context's scratch pools back to the device's stream-ordered
+ * allocator when they hold more than keep_bytes together (pool A is kept
+ * when it alone fits).  The memory is released after the context's last
+ * call completes, without waiting for it on the host or on other streams;
+ * the next call grows the pools again. */
+int drf_ctx_release(drf_ctx *ctx, uint64_t keep_bytes);
+
+/* Check one protocol.  Defines: Definition 1 (a phase is racy when two
+ * distinct threads access one index in it and one of them writes), applied
+ * to every phase of the protocol's synchronized execution (Section 2;
+ * threads run independently, rule par of Fig. "Syntax and semantics of
+ * BabyCUDA").
+ * d_result: one drf_result in device memory.  d_phase_counts: device array
+ * of phase_cap u64 (needs plan.num_phases).  stream: hipStream_t (NULL =
+ * default stream).  Returns DRF_OK once the work is enqueued (see
+ * Asynchrony), DRF_E_ARG for missing pointers or phase_cap too small,
+ * DRF_E_NOMEM when the scratch limit cannot hold the call's metadata,
+ * DRF_E_HIP for a HIP failure.  After a call-level
+ * error nothing has been written to d_result / d_phase_counts (DRF_E_HIP
+ * from a failed launch excepted) and the context stays usable. */
 int drf_check_protocol(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads,
                        drf_result *d_result, uint64_t *d_phase_counts, uint64_t phase_cap,
                        void *stream);
 
-/* Check `count` protocols in one launch sequence.  Protocol i's bytecode is
+/* Check `count` protocols in one launch sequence (same definition as
+ * drf_check_protocol, per protocol).  Protocol i's bytecode is
  * code[code_off[i] .. code_off[i+1]) (code_off has count+1 entries), run by
  * nthreads[i] threads.  d_results: count drf_result (device).
  * d_phase_counts: device array of phase_cap u64; protocol i's counts start
  * at the sum of num_phases of protocols 0..i-1 (its plan's num_phases;
- * protocols with status != 0 take none). */
+ * protocols with status != 0 take none).  A protocol whose single phase
+ * cannot fit the scratch limit gets status DRF_E_NOMEM; the others are
+ * still checked.  Return codes as for drf_check_protocol. */
 int drf_check_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off,
                     const uint32_t *nthreads, uint32_t count,
                     drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
                     void *stream);
+
+/* ---------------------------------------------------- parameter sweeps
+ * A protocol may mention a free parameter (the racy example of Section 2
+ * loops up to a symbolic M, typed under the context {M, tid} in Section 4).
+ * The paper reasons about every M symbolically; these calls check the
+ * concrete instances p[M := v] for v = first .. first + count - 1 as one
+ * batch.  The parameter is a variable slot that no loop binds. */
+
+/* Slot the text compiler gives variable `name` in `text` (names get slots
+ * in order of first appearance).  DRF_E_ARG when the text does not compile
+ * or never mentions the name.  Host only. */
+int drf_text_slot(const char *text, size_t len, const char *name, uint32_t *slot);
+
+/* Bytecode of the protocol with every occurrence of variable `slot`
+ * replaced by the constant `value` (out/cap/nwords as drf_compile_text).
+ * DRF_E_ARG when a loop binds the slot; the bytecode's own problems as
+ * DRF_E_BYTECODE.  Host only. */
+int drf_bind_param(const uint32_t *code, uint32_t words, uint32_t slot, uint64_t value, uint32_t *out,
+                   uint32_t cap, uint32_t *nwords);
+
+/* Plans of the count instances (as drf_plan_batch); instance i's phase
+ * counts start at the sum of num_phases of instances 0..i-1. */
+int drf_plan_sweep(const uint32_t *code, uint32_t words, uint32_t num_threads, uint32_t slot, uint64_t first,
+                   uint32_t count, drf_plan *plans, uint64_t *scratch_bytes_total);
+
+/* Check the count instances in one launch sequence: d_results[i] is the
+ * result of p[slot := first + i] (layout and return codes as
+ * drf_check_batch). */
+int drf_check_sweep(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads, uint32_t slot,
+                    uint64_t first, uint32_t count, drf_result *d_results, uint64_t *d_phase_counts,
+                    uint64_t phase_cap, void *stream);
+
+/* ------------------------------------------------ several shared arrays
+ * The analysis gives one behavioural type per shared array (Section 3,
+ * Syntax): accesses to different arrays never race.  In the bytecode the
+ * ACC mode word carries the array in its upper bits (write | array << 1;
+ * text form rd:A / wr:A, arrays numbered in order of first appearance, the
+ * plain rd / wr counting as one of them).  The planning and checking calls
+ * above give such a protocol the status DRF_E_MULTI; these calls check one
+ * protocol per array. */
+
+/* Number of arrays the protocol accesses (1 + the largest array id; 1 for
+ * a protocol without accesses).  Host only. */
+int drf_protocol_arrays(const uint32_t *code, uint32_t words, uint32_t *num_arrays);
+
+/* Plans of every array's protocol (cap: entries of plans; DRF_E_ARG when
+ * the protocol has more arrays). */
+int drf_plan_arrays(const uint32_t *code, uint32_t words, uint32_t num_threads, drf_plan *plans, uint32_t cap,
+                    uint64_t *scratch_bytes_total);
+
+/* Check every array's protocol (the protocol with the other arrays'
+ * accesses replaced by skip) in one launch sequence: d_results[a] and the
+ * phase counts of array a (num_phases u64 each, array after array) as
+ * drf_check_batch lays them out.  Defined by Definition 1 per array. */
+int drf_check_arrays(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads,
+                     drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap, void *stream);
+
+/* ------------------------------------------------- BabyCUDA front end
+ * Infers the memory access protocol of a BabyCUDA program (Section 3, Fig.
+ * "Syntax and semantics of BabyCUDA") with the behavioural type system of
+ * Section 4 (Fig. "Behavioral type system": V |- b |> u, rules t-n, t-b,
+ * t-write, t-read, t-seq, t-if, t-for, t-skip), V = {tid} plus `params`
+ * (space-separated parameter names, e.g. "M"; NULL for none).  By Theorem 1
+ * a well-typed program is DRF exactly when its protocol is, so the
+ * protocol can be checked in its place.  Text form of programs:
+ *   (skip) (sync) (wr n n') (rd y n b) (seq b ...) (if c b b) (for x n n b)
+ * with wr:A / rd:A for several arrays; the protocol comes out in the text
+ * form of drf_compile_text (loops holding a sync become for^S).
+ * Returns DRF_E_ARG when the text is not a BabyCUDA program, else DRF_OK
+ * with *status 0 (out holds the NUL-terminated protocol; *needed its size
+ * with the NUL; DRF_E_NOMEM when cap is smaller) or a typing status:
+ *   DRF_E_ILLTYPED  a variable bound by a read reaches an index, guard or
+ *                   loop bound (data-dependent access, the ill-typed
+ *                   example of Section 4)
+ *   DRF_E_UNBOUND   a variable no binder or parameter introduces
+ *   DRF_E_SHADOW    a binder that is not fresh (nested binders distinct)
+ * Host only. */
+int drf_babycuda_infer(const char *text, size_t len, const char *params, char *out, size_t cap, size_t *needed,
+                       int32_t *status);
 
 /* Per-kernel timing of a context (for measurement).  When enabled, every
  * kernel launch is bracketed by HIP events recorded on the call's stream;
@@ -181,8 +319,9 @@ typedef struct {
 } drf_kernel_stat;         /* 48 bytes */
 
 int drf_ctx_set_profiling(drf_ctx *ctx, int on);
-/* Copies up to cap entries into out, sets *n to the number of classes and
- * resets the totals when reset != 0. */
+/* Waits on the host for the context's last call, then copies up to cap
+ * entries into out, sets *n to the number of classes and resets the totals
+ * when reset != 0. */
 int drf_ctx_kernel_stats(drf_ctx *ctx, drf_kernel_stat *out, uint32_t cap, uint32_t *n, int reset);
 
 /* Prepared batch: checks the batch once (like drf_check_batch, with the

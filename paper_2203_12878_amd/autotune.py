@@ -7,8 +7,12 @@ tunings by coordinate descent over
     unit_events  (events per fused unit)
     item_events  (events per count / emit work item)
 and keeps the fastest.  Results are cached per size class of the workload
-(log2 of its access events, log2 of its protocol count, whether it has
-phases above one tile) in a JSON file, which Checker.tune_for() consults.
+(log2 of its planned access events, log2 of its protocol count, whether it
+has phases above one tile) in a JSON file; apply_cached() sets the cached
+tuning of a batch's size class on a Checker.  The package ships the cache
+of the tunings measured on an MI355X (tuning.json next to this file);
+DRF_TUNING_CACHE points elsewhere.  Tunings never change results, only
+speed.
 """
 from __future__ import annotations
 
@@ -27,7 +31,7 @@ SPACE = {
     "item_events": [1 << 14, 1 << 16, 1 << 18],
 }
 DEFAULT = {"tile_events": 8192, "digit_bits": 10, "unit_events": 1 << 15, "item_events": 1 << 16}
-CACHE = os.environ.get("DRF_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "drf_tuning.json"))
+CACHE = os.environ.get("DRF_TUNING_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
 
 
 def size_class(batch: "drf.Batch") -> str:
@@ -45,7 +49,7 @@ def load_cache(path: str = CACHE) -> Dict[str, dict]:
 
 
 def save_cache(cache: Dict[str, dict], path: str = CACHE) -> None:
-    os.makedirs(os.path.dirname(path), exist_ok=True)
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libdrf.so; always recompiles."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, is_hip in (("host.cpp", False), ("api.cpp", False), ("kernels.hip", True)):
+    for src, is_hip in (("host.cpp", False), ("babycuda.cpp", False), ("api.cpp", False), ("kernels.hip", True)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + COMMON + ["--offload-arch=" + ARCH] + DEVICE_FLAGS
         cmd += (["-x", "hip"] if is_hip else []) + ["-c", os.path.join(CSRC, src), "-o", obj]

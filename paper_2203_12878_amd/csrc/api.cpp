@@ -31,6 +31,7 @@
 #include <thread>
 #include <tuple>
 #include <initializer_list>
+#include <new>
 #include <vector>
 
 #include "../../include/drf.h"
@@ -165,16 +166,23 @@ void prof_collect(drf_ctx *c) {
     c->pending.clear();
 }
 
-void grow(void *&p, size_t &size, size_t need) {
+// Grows one of the context's two pools to at least `need` bytes, keeping
+// both pools together within the context's limit (DRF_E_NOMEM beyond it).
+// The old block is released and the new one taken in stream order on the
+// call's stream (which already waits for the context's previous call), so
+// no other stream or context is stalled.  Contents are not preserved.
+void grow(drf_ctx *c, void *&p, size_t &size, size_t need, hipStream_t st) {
     if (need <= size) return;
+    const uint64_t other = c->sizeA + c->sizeB - size;
+    size_t want = (need + (64ull << 20) - 1) & ~((64ull << 20) - 1);
+    if (other + want > c->limit) want = (need + ALIGN - 1) & ~(ALIGN - 1);
+    if (other + want > c->limit) throw Fail{DRF_E_NOMEM};
     if (p) {
-        hipck(hipDeviceSynchronize());
-        hipck(hipFree(p));
+        hipck(hipFreeAsync(p, st));
         p = nullptr;
         size = 0;
     }
-    size_t want = (need + (64ull << 20) - 1) & ~((64ull << 20) - 1);
-    if (hipMalloc(&p, want) != hipSuccess) {
+    if (hipMallocAsync(&p, want, st) != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();
         throw Fail{DRF_E_NOMEM};
@@ -248,17 +256,21 @@ struct Recorder {
     std::vector<void *> owned;     // device allocations kept for the replays
     char *arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
+    uint64_t limit = ~0ull, total = 0;   // bytes the recording may own, and owns
 
     void *alloc(size_t bytes) {
         size_t off = (arena_used + ALIGN - 1) & ~(ALIGN - 1);
         if (!arena || off + bytes > arena_cap) {
-            const size_t cap = std::max<size_t>(bytes + ALIGN, 64ull << 20);
+            size_t cap = std::max<size_t>(bytes + ALIGN, 64ull << 20);
+            if (total + cap > limit) cap = bytes + ALIGN;
+            if (total + cap > limit) throw Fail{DRF_E_NOMEM};
             void *p = nullptr;
             if (hipMalloc(&p, cap) != hipSuccess) {
                 (void)hipGetLastError();
                 throw Fail{DRF_E_NOMEM};
             }
             owned.push_back(p);
+            total += cap;
             arena = (char *)p;
             arena_cap = cap;
             off = 0;
@@ -532,7 +544,7 @@ WaveLayout wave_layout(uint64_t recs, uint64_t win_n, uint64_t nbig, uint64_t ni
     L.o_cur = b.reserve(win_n * 8);
     L.o_ra = b.reserve(recs * 8);
     L.o_rb = b.reserve(recs * 8);
-    L.o_hist = b.reserve((L.hist_max + scan_tmp_words(L.hist_max)) * 8);
+    L.o_hist = b.reserve(L.hist_max * 8);
     L.o_starts = b.reserve(L.nsegs_max * L.sstride * 8);
     L.o_segs = b.reserve(L.nsegs_max * sizeof(Seg));
     L.o_chunks = b.reserve(L.chunks_max * sizeof(Chunk));
@@ -804,8 +816,7 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         if (!g2.empty()) run_groups(g2, out);
         segs.swap(next);
         std::swap(in, out);
-        C.sync();
-        C.tr.mark("level tiles done", tiles.size());
+        C.tr.mark("level tiles launched", tiles.size());
     }
 }
 
@@ -820,7 +831,6 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
     C.count = count;
     C.rec = rec;
     C.keep.ctx = ctx;
-    C.keep.clear();   // the previous call on this context ended with its stream drained
     try {
         hipck(hipSetDevice(ctx->device));
         if (ctx->done_valid) hipck(hipStreamWaitEvent(st, ctx->done, 0));
@@ -831,7 +841,13 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         if (C.total_phases > phase_cap || (C.total_phases && !d_phase_counts)) return DRF_E_ARG;
         // upper bound on fused units: one per small phase at most
         C.layout_a(C.total_phases + 1);
-        grow(ctx->poolA, ctx->sizeA, C.needA);
+        // the previous call's device work may still read the pinned staging
+        // and read-back buffers: wait for it on the host before reusing them
+        // (planning above overlapped with it)
+        if (ctx->done_valid) hipck(hipEventSynchronize(ctx->done));
+        prof_collect(ctx);
+        C.keep.clear();
+        grow(ctx, ctx->poolA, ctx->sizeA, C.needA, st);
         void *A = ctx->poolA;
         unsigned long long *phase_counts = (unsigned long long *)d_phase_counts;
         Best *best = at<Best>(A, C.o_best);
@@ -1044,50 +1060,62 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
 
         // ---- big phases, in waves under the scratch budget
         if (!big.empty()) {
-            const uint64_t budget = ctx->limit > C.needA ? ctx->limit - C.needA : 0;
-            const uint64_t per_rec = 20;   // two record buffers + partition metadata
-            const uint64_t rec_cap = budget / per_rec;
+            const uint64_t budget = ctx->limit > ctx->sizeA ? ctx->limit - ctx->sizeA : 0;
+            // records per wave: about 21 bytes of pool B per record (two
+            // record buffers and the partition metadata); the cap shrinks
+            // until the largest wave's layout fits the budget
+            uint64_t rec_cap = budget / 24;
             std::vector<Wave> waves;
-            size_t bi = 0;
-            while (bi < big.size()) {
-                if (big[bi].count > rec_cap) {   // a phase that can never fit
-                    C.status[big[bi].proto] = DRF_E_NOMEM;
-                    bi++;
-                    continue;
-                }
-                Wave W;
-                W.bi = bi;
-                W.recs = 0;
-                size_t be = bi;
-                while (be < big.size() && big[be].count <= rec_cap && W.recs + big[be].count <= rec_cap &&
-                       big[be].k - big[bi].k < (1ull << 26)) {
-                    W.recs += big[be].count;
-                    be++;
-                }
-                W.be = be;
-                waves.push_back(std::move(W));
-                bi = be;
-            }
-            // one wave takes every item as uploaded; several take the items
-            // overlapping their phase window
-            if (waves.size() == 1) {
-                waves[0].all = true;
-            } else {
-                for (Wave &W : waves) {
-                    const uint64_t win_lo = big[W.bi].k, win_n = big[W.be - 1].k - win_lo + 1;
-                    for (int w = 0; w < 2; w++)
-                        for (const Item &it : C.items[w])
-                            if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) W.witems[w].push_back(it);
-                }
-            }
             size_t needB = 0;
-            for (const Wave &W : waves) {
-                const uint64_t win_n = big[W.be - 1].k - big[W.bi].k + 1;
-                needB = std::max(needB, wave_layout(W.recs, win_n, W.be - W.bi, W.witems[0].size(),
-                                                    W.witems[1].size(), ctx->tune.tile_events, small,
-                                                    ctx->tune.digit_bits).bytes);
+            for (int attempt = 0;; attempt++) {
+                waves.clear();
+                std::vector<int32_t> st_try = C.status;
+                size_t bi = 0;
+                while (bi < big.size()) {
+                    if (big[bi].count > rec_cap) {   // a phase that can never fit
+                        st_try[big[bi].proto] = DRF_E_NOMEM;
+                        bi++;
+                        continue;
+                    }
+                    Wave W;
+                    W.bi = bi;
+                    W.recs = 0;
+                    size_t be = bi;
+                    while (be < big.size() && big[be].count <= rec_cap && W.recs + big[be].count <= rec_cap &&
+                           big[be].k - big[bi].k < (1ull << 26)) {
+                        W.recs += big[be].count;
+                        be++;
+                    }
+                    W.be = be;
+                    waves.push_back(std::move(W));
+                    bi = be;
+                }
+                // one wave takes every item as uploaded; several take the
+                // items overlapping their phase window
+                if (waves.size() == 1) {
+                    waves[0].all = true;
+                } else {
+                    for (Wave &W : waves) {
+                        const uint64_t win_lo = big[W.bi].k, win_n = big[W.be - 1].k - win_lo + 1;
+                        for (int w = 0; w < 2; w++)
+                            for (const Item &it : C.items[w])
+                                if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) W.witems[w].push_back(it);
+                    }
+                }
+                needB = 0;
+                for (const Wave &W : waves) {
+                    const uint64_t win_n = big[W.be - 1].k - big[W.bi].k + 1;
+                    needB = std::max(needB, wave_layout(W.recs, win_n, W.be - W.bi, W.witems[0].size(),
+                                                        W.witems[1].size(), ctx->tune.tile_events, small,
+                                                        ctx->tune.digit_bits).bytes);
+                }
+                if (needB <= budget || rec_cap == 0 || attempt == 8) {
+                    C.status.swap(st_try);
+                    break;
+                }
+                rec_cap = (uint64_t)((double)rec_cap * ((double)budget / (double)needB) * 0.98);
             }
-            grow(ctx->poolB, ctx->sizeB, needB);
+            grow(ctx, ctx->poolB, ctx->sizeB, needB, st);
             C.tr.mark("waves planned", waves.size());
             for (const Wave &W : waves) run_wave(C, big, W, best, cand);
             C.tr.mark("waves done");
@@ -1110,11 +1138,9 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         if (!ctx->done) hipck(hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming));
         hipck(hipEventRecord(ctx->done, st));
         ctx->done_valid = true;
-        // pageable uploads are staged synchronously; the last ones must
-        // still be complete before the host copies go away
-        hipck(hipStreamSynchronize(st));
-        C.tr.mark("done");
-        prof_collect(ctx);
+        // every upload came from pinned staging that the context keeps until
+        // its next call has waited for this event: return without waiting
+        C.tr.mark("enqueued");
         return DRF_OK;
     } catch (Fail f) {
         (void)hipGetLastError();
@@ -1123,6 +1149,52 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
     } catch (...) {
         (void)hipStreamSynchronize(st);
         return DRF_E_NOMEM;
+    }
+}
+
+// Device scratch one call checking these plans may take: pool A (the
+// uploaded metadata, per-phase bookkeeping and witness candidates) plus pool
+// B for every record of the phases above one tile in a single wave.  The
+// tuning of `tuned` is used (the library default when null).  An upper
+// bound: the count pass may find fewer big-phase records than the plans
+// allow, and a context whose limit is smaller splits the records into
+// waves instead.
+uint64_t scratch_estimate(const drf_ctx *tuned, std::vector<Plan> &&plans) {
+    drf_ctx tmp;
+    if (tuned) {
+        tmp.tune = tuned->tune;
+        tmp.cus = tuned->cus;
+    }
+    Call C;
+    C.ctx = &tmp;
+    C.count = (uint32_t)plans.size();
+    C.plans = std::move(plans);
+    C.build_blob();
+    C.layout_a(C.total_phases + 1);
+    const uint32_t small = small_events(&tmp);
+    uint64_t bigrec = 0, nbig = 0;
+    for (const Plan &p : C.plans) {
+        if (p.status || p.max_phase_records <= (uint64_t)small) continue;
+        bigrec += std::min<uint64_t>(p.max_records, 1ull << 40);
+        nbig += p.num_phases;
+    }
+    uint64_t b = 0;
+    if (bigrec)
+        b = wave_layout(bigrec, nbig, nbig, C.items[0].size(), C.items[1].size(), tmp.tune.tile_events, small,
+                        tmp.tune.digit_bits).bytes;
+    return C.needA + b;
+}
+
+void fill_plan(const Plan &p, drf_plan *out) {
+    memset(out, 0, sizeof *out);
+    out->status = p.status;
+    if (!p.status) {
+        out->num_phases = (uint32_t)p.num_phases;
+        out->index_bits = p.index_bits;
+        out->wide = p.wide ? 1 : 0;
+        out->max_records = p.max_records;
+        out->nests = p.nests.size();
+        out->max_phase_records = p.max_phase_records;
     }
 }
 
@@ -1135,30 +1207,56 @@ const char *drf_version(void) { return "libdrf 0.1 (gfx950)"; }
 
 int drf_compile_text(const char *text, size_t len, uint32_t *out, uint32_t cap, uint32_t *nwords) {
     if (!text || !nwords) return DRF_E_ARG;
-    std::vector<uint32_t> w;
-    int rc = compile_text(text, len, w);
-    if (rc) return rc;
-    *nwords = (uint32_t)w.size();
-    if (w.size() > cap || !out) return DRF_E_NOMEM;
-    memcpy(out, w.data(), w.size() * sizeof(uint32_t));
-    return DRF_OK;
+    try {
+        std::vector<uint32_t> w;
+        int rc = compile_text(text, len, w);
+        if (rc) return rc;
+        *nwords = (uint32_t)w.size();
+        if (w.size() > cap || !out) return DRF_E_NOMEM;
+        memcpy(out, w.data(), w.size() * sizeof(uint32_t));
+        return DRF_OK;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
 }
 
 int drf_plan_protocol(const uint32_t *code, uint32_t words, uint32_t num_threads, drf_plan *out) {
     if (!out) return DRF_E_ARG;
-    Plan p;
-    plan_protocol(code, words, num_threads, p);
-    memset(out, 0, sizeof *out);
-    out->status = p.status;
-    if (!p.status) {
-        out->num_phases = (uint32_t)p.num_phases;
-        out->index_bits = p.index_bits;
-        out->wide = p.wide ? 1 : 0;
-        out->max_records = p.max_records;
-        out->nests = p.nests.size();
-        out->max_phase_records = p.max_phase_records;
+    try {
+        std::vector<Plan> ps(1);
+        plan_protocol(code, words, num_threads, ps[0]);
+        fill_plan(ps[0], out);
+        out->scratch_bytes = scratch_estimate(nullptr, std::move(ps));
+        return DRF_OK;
+    } catch (...) {
+        memset(out, 0, sizeof *out);
+        return DRF_E_NOMEM;
     }
-    return DRF_OK;
+}
+
+int drf_plan_batch(const drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                   uint32_t count, drf_plan *plans, uint64_t *scratch_bytes_total) {
+    if (!code_off || !nthreads || (count && (!code || !plans))) return DRF_E_ARG;
+    try {
+        drf_ctx tmp;
+        if (ctx) {
+            tmp.tune = ctx->tune;
+            tmp.cus = ctx->cus;
+        }
+        Call C;
+        C.ctx = &tmp;
+        C.count = count;
+        C.plan_all(code, code_off, nthreads);
+        for (uint32_t i = 0; i < count; i++) {
+            fill_plan(C.plans[i], &plans[i]);
+            std::vector<Plan> one(1, C.plans[i]);
+            plans[i].scratch_bytes = scratch_estimate(&tmp, std::move(one));
+        }
+        if (scratch_bytes_total) *scratch_bytes_total = count ? scratch_estimate(&tmp, std::move(C.plans)) : 0;
+        return DRF_OK;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
 }
 
 int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out) {
@@ -1170,7 +1268,8 @@ int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out) 
         return DRF_E_HIP;
     }
     if (hipSetDevice(hip_device) != hipSuccess) return DRF_E_HIP;
-    drf_ctx *c = new drf_ctx();
+    drf_ctx *c = new (std::nothrow) drf_ctx();
+    if (!c) return DRF_E_NOMEM;
     c->device = hip_device;
     if (scratch_limit_bytes == 0) {
         size_t fr = 0, tot = 0;
@@ -1185,12 +1284,48 @@ int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out) 
     return DRF_OK;
 }
 
+int drf_ctx_release(drf_ctx *ctx, uint64_t keep_bytes) {
+    if (!ctx) return DRF_E_ARG;
+    if (ctx->sizeA + ctx->sizeB <= keep_bytes) return DRF_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return DRF_E_HIP;
+    // freed in stream order after the context's last call, on a stream of
+    // its own, so that neither the host nor other streams wait
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return DRF_E_HIP;
+    }
+    int rc = DRF_OK;
+    if (ctx->done_valid && hipStreamWaitEvent(st, ctx->done, 0) != hipSuccess) rc = DRF_E_HIP;
+    if (rc == DRF_OK && ctx->poolB) {
+        if (hipFreeAsync(ctx->poolB, st) == hipSuccess) {
+            ctx->poolB = nullptr;
+            ctx->sizeB = 0;
+        } else {
+            rc = DRF_E_HIP;
+        }
+    }
+    if (rc == DRF_OK && ctx->poolA && ctx->sizeA > keep_bytes) {
+        if (hipFreeAsync(ctx->poolA, st) == hipSuccess) {
+            ctx->poolA = nullptr;
+            ctx->sizeA = 0;
+        } else {
+            rc = DRF_E_HIP;
+        }
+    }
+    (void)hipStreamDestroy(st);
+    if (rc != DRF_OK) (void)hipGetLastError();
+    return rc;
+}
+
 int drf_ctx_destroy(drf_ctx *ctx) {
     if (!ctx) return DRF_E_ARG;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->poolA) (void)hipFree(ctx->poolA);
-    if (ctx->poolB) (void)hipFree(ctx->poolB);
+    // the pools come from the stream-ordered allocator
+    if (ctx->poolA) (void)hipFreeAsync(ctx->poolA, nullptr);
+    if (ctx->poolB) (void)hipFreeAsync(ctx->poolB, nullptr);
+    (void)hipDeviceSynchronize();
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->counted) (void)hipEventDestroy(ctx->counted);
     if (ctx->parted) (void)hipEventDestroy(ctx->parted);
@@ -1238,6 +1373,14 @@ int drf_ctx_get_tuning(drf_ctx *ctx, drf_tuning *t) {
 
 int drf_ctx_kernel_stats(drf_ctx *ctx, drf_kernel_stat *out, uint32_t cap, uint32_t *n, int reset) {
     if (!ctx || !n) return DRF_E_ARG;
+    if (ctx->done_valid) {
+        (void)hipSetDevice(ctx->device);
+        if (hipEventSynchronize(ctx->done) != hipSuccess) {
+            (void)hipGetLastError();
+            return DRF_E_HIP;
+        }
+    }
+    prof_collect(ctx);
     *n = K_NCLASS;
     for (uint32_t i = 0; i < K_NCLASS && i < cap && out; i++) {
         out[i] = ctx->stats[i];
@@ -1277,6 +1420,7 @@ int drf_prepare_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_o
     p->priv->limit = ctx->limit;
     p->priv->tune = ctx->tune;
     p->priv->cus = ctx->cus;
+    p->rec.limit = ctx->limit;
     int rc = check_impl(p->priv, code, code_off, nthreads, count, d_results, d_phase_counts, phase_cap,
                         (hipStream_t)stream, &p->rec);
     if (rc != DRF_OK) {
@@ -1315,6 +1459,179 @@ int drf_run_prepared(drf_prepared *p, void *stream) {
 }
 
 uint64_t drf_prepared_launches(const drf_prepared *p) { return p ? p->rec.ops.size() : 0; }
+
+int drf_babycuda_infer(const char *text, size_t len, const char *params, char *out, size_t cap, size_t *needed,
+                       int32_t *status) {
+    if (!text || !needed || !status) return DRF_E_ARG;
+    try {
+        std::string map;
+        const int st = babycuda_infer(text, len, params, map);
+        if (st == DRF_E_ARG) return DRF_E_ARG;
+        *status = st;
+        *needed = st ? 0 : map.size() + 1;
+        if (st) return DRF_OK;
+        if (!out || cap < map.size() + 1) return DRF_E_NOMEM;
+        memcpy(out, map.c_str(), map.size() + 1);
+        return DRF_OK;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+int drf_text_slot(const char *text, size_t len, const char *name, uint32_t *slot) {
+    if (!text || !name || !slot) return DRF_E_ARG;
+    try {
+        const int s2 = text_slot(text, len, name);
+        if (s2 < 0) return DRF_E_ARG;
+        *slot = (uint32_t)s2;
+        return DRF_OK;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+int drf_protocol_arrays(const uint32_t *code, uint32_t words, uint32_t *num_arrays) {
+    if (!num_arrays) return DRF_E_ARG;
+    try {
+        IR ir;
+        const int st = decode(code, words, ir);
+        if (st) return st;
+        *num_arrays = ir_arrays(ir);
+        return DRF_OK;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+int drf_bind_param(const uint32_t *code, uint32_t words, uint32_t slot, uint64_t value, uint32_t *out,
+                   uint32_t cap, uint32_t *nwords) {
+    if (!nwords) return DRF_E_ARG;
+    try {
+        IR ir;
+        const int st = decode(code, words, ir);
+        if (st) return st;
+        if (slot >= ir.nslots || !ir_bind(ir, slot, value)) return DRF_E_ARG;
+        std::vector<uint32_t> w;
+        encode(ir, w);
+        *nwords = (uint32_t)w.size();
+        if (w.size() > cap || !out) return DRF_E_NOMEM;
+        memcpy(out, w.data(), w.size() * sizeof(uint32_t));
+        return DRF_OK;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+namespace {
+
+// The instances of a parameter sweep, packed as a batch: instance i is the
+// protocol with variable `slot` bound to first + i.
+int sweep_codes(const uint32_t *code, uint32_t words, uint32_t slot, uint64_t first, uint32_t count,
+                std::vector<uint32_t> &all, std::vector<uint64_t> &off) {
+    IR ir;
+    const int st = decode(code, words, ir);
+    if (st) return st;
+    if (slot >= ir.nslots) return DRF_E_ARG;
+    for (const SNode &s2 : ir.s)
+        if ((s2.kind == B_FORU || s2.kind == B_FORS) && s2.slot == slot) return DRF_E_ARG;
+    if (count && first + (uint64_t)(count - 1) < first) return DRF_E_ARG;
+    off.assign(1, 0);
+    std::vector<uint32_t> w;
+    for (uint32_t i = 0; i < count; i++) {
+        IR c = ir;
+        ir_bind(c, slot, first + i);
+        encode(c, w);
+        all.insert(all.end(), w.begin(), w.end());
+        off.push_back(all.size());
+    }
+    return DRF_OK;
+}
+
+// The protocol of each array of a multi-array protocol, packed as a batch.
+int array_codes(const uint32_t *code, uint32_t words, std::vector<uint32_t> &all, std::vector<uint64_t> &off) {
+    IR ir;
+    const int st = decode(code, words, ir);
+    if (st) return st;
+    const uint32_t na = ir_arrays(ir);
+    off.assign(1, 0);
+    std::vector<uint32_t> w;
+    for (uint32_t a = 0; a < na; a++) {
+        IR c = ir;
+        ir_project(c, a);
+        encode(c, w);
+        all.insert(all.end(), w.begin(), w.end());
+        off.push_back(all.size());
+    }
+    return DRF_OK;
+}
+
+}  // namespace
+
+int drf_plan_sweep(const uint32_t *code, uint32_t words, uint32_t num_threads, uint32_t slot, uint64_t first,
+                   uint32_t count, drf_plan *plans, uint64_t *scratch_bytes_total) {
+    if (count && !plans) return DRF_E_ARG;
+    try {
+        std::vector<uint32_t> all;
+        std::vector<uint64_t> off;
+        const int rc = sweep_codes(code, words, slot, first, count, all, off);
+        if (rc) return rc;
+        std::vector<uint32_t> nth(count, num_threads);
+        return drf_plan_batch(nullptr, all.data(), off.data(), nth.data(), count, plans, scratch_bytes_total);
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+int drf_check_sweep(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads, uint32_t slot,
+                    uint64_t first, uint32_t count, drf_result *d_results, uint64_t *d_phase_counts,
+                    uint64_t phase_cap, void *stream) {
+    if (!ctx) return DRF_E_ARG;
+    try {
+        std::vector<uint32_t> all;
+        std::vector<uint64_t> off;
+        const int rc = sweep_codes(code, words, slot, first, count, all, off);
+        if (rc) return rc;
+        std::vector<uint32_t> nth(count, num_threads);
+        return check_impl(ctx, all.data(), off.data(), nth.data(), count, d_results, d_phase_counts, phase_cap,
+                          (hipStream_t)stream);
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+int drf_plan_arrays(const uint32_t *code, uint32_t words, uint32_t num_threads, drf_plan *plans, uint32_t cap,
+                    uint64_t *scratch_bytes_total) {
+    if (!plans) return DRF_E_ARG;
+    try {
+        std::vector<uint32_t> all;
+        std::vector<uint64_t> off;
+        const int rc = array_codes(code, words, all, off);
+        if (rc) return rc;
+        const uint32_t na = (uint32_t)(off.size() - 1);
+        if (na > cap) return DRF_E_ARG;
+        std::vector<uint32_t> nth(na, num_threads);
+        return drf_plan_batch(nullptr, all.data(), off.data(), nth.data(), na, plans, scratch_bytes_total);
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
+
+int drf_check_arrays(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads,
+                     drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap, void *stream) {
+    if (!ctx) return DRF_E_ARG;
+    try {
+        std::vector<uint32_t> all;
+        std::vector<uint64_t> off;
+        const int rc = array_codes(code, words, all, off);
+        if (rc) return rc;
+        const uint32_t na = (uint32_t)(off.size() - 1);
+        std::vector<uint32_t> nth(na, num_threads);
+        return check_impl(ctx, all.data(), off.data(), nth.data(), na, d_results, d_phase_counts, phase_cap,
+                          (hipStream_t)stream);
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
 
 int drf_check_protocol(drf_ctx *ctx, const uint32_t *code, uint32_t words, uint32_t num_threads,
                        drf_result *d_result, uint64_t *d_phase_counts, uint64_t phase_cap, void *stream) {

@@ -27,6 +27,7 @@ struct TextCompiler {
     size_t n, pos = 0;
     bool err = false;
     std::unordered_map<std::string, uint32_t> slots;
+    std::unordered_map<std::string, uint32_t> arrays;   // "" is the unnamed array
     std::vector<uint32_t> out;
 
     static bool is_space(char c) { return c == ' ' || c == '\t' || c == '\n' || c == '\r'; }
@@ -152,9 +153,17 @@ struct TextCompiler {
         if (!next(h)) { err = true; return; }
         if (h == "skip") out.push_back(B_SKIP);
         else if (h == "sync") out.push_back(B_SYNC);
-        else if (h == "rd" || h == "wr") {
+        else if (h == "rd" || h == "wr" || h.compare(0, 3, "rd:") == 0 || h.compare(0, 3, "wr:") == 0) {
+            // rd / wr access "the" array; rd:A / wr:A name one of several
+            // arrays (ids in order of first appearance, the unnamed one too)
+            const std::string name = h.size() > 2 ? h.substr(3) : std::string();
+            if (h.size() > 2 && !ident(name)) { err = true; return; }
+            auto it = arrays.find(name);
+            const uint32_t id = it != arrays.end() ? it->second : (uint32_t)arrays.size();
+            if (it == arrays.end()) arrays.emplace(name, id);
+            if (id >= MAX_ARRAYS) { err = true; return; }
             out.push_back(B_ACC);
-            out.push_back(h == "wr" ? 1u : 0u);
+            out.push_back((h[0] == 'w' ? 1u : 0u) | id << 1);
             block(false);
         } else if (h == "seq") {
             out.push_back(B_SEQ);
@@ -188,6 +197,17 @@ struct TextCompiler {
 };
 
 }  // namespace
+
+int text_slot(const char *text, size_t len, const char *name) {
+    TextCompiler c;
+    c.s = text;
+    c.n = len;
+    c.stmt();
+    std::string t;
+    if (c.err || c.next(t)) return -1;
+    auto it = c.slots.find(name);
+    return it == c.slots.end() ? -1 : (int)it->second;
+}
 
 int compile_text(const char *text, size_t len, std::vector<uint32_t> &words) {
     TextCompiler c;
@@ -289,8 +309,9 @@ struct Decoder {
         case B_SKIP: case B_SYNC: break;
         case B_ACC:
             if (pos >= n) { bad(); break; }
-            s.mode = w[pos++];
-            if (s.mode > 1) { bad(); break; }
+            s.mode = w[pos] & 1u;
+            s.array = w[pos++] >> 1;
+            if (s.array >= MAX_ARRAYS) { bad(); break; }
             s.e = expr(false);
             break;
         case B_SEQ: {
@@ -1067,6 +1088,8 @@ int plan_protocol(const uint32_t *code, uint32_t words, uint32_t n, Plan &plan) 
     IR ir;
     int st = decode(code, words, ir);
     if (!st) st = static_check(ir);
+    // several arrays: one protocol per array (drf_check_arrays)
+    if (!st && ir_arrays(ir) > 1) st = DRF_E_MULTI;
     if (st) { plan.status = st; return 0; }
     Planner p(ir, n, plan);
     p.run();
@@ -1077,6 +1100,109 @@ int plan_protocol(const uint32_t *code, uint32_t words, uint32_t n, Plan &plan) 
         plan.status = s2;
     }
     return 0;
+}
+
+// ================================================== rewriting of protocols
+namespace {
+
+void enc_expr(const IR &ir, int e, std::vector<uint32_t> &w) {
+    const XNode &x = ir.x[e];
+    if (x.a >= 0) enc_expr(ir, x.a, w);
+    if (x.b >= 0) enc_expr(ir, x.b, w);
+    switch (x.op) {
+    case B_CONST32: case B_CONST64:
+        if (x.val < (1ull << 32)) {
+            w.push_back(B_CONST32);
+            w.push_back((uint32_t)x.val);
+        } else {
+            w.push_back(B_CONST64);
+            w.push_back((uint32_t)x.val);
+            w.push_back((uint32_t)(x.val >> 32));
+        }
+        break;
+    case B_VAR:
+        w.push_back(B_VAR);
+        w.push_back(x.slot);
+        break;
+    default: w.push_back(x.op); break;
+    }
+}
+
+void enc_block(const IR &ir, int e, std::vector<uint32_t> &out) {
+    std::vector<uint32_t> w;
+    enc_expr(ir, e, w);
+    out.push_back((uint32_t)w.size());
+    out.insert(out.end(), w.begin(), w.end());
+}
+
+void enc_stmt(const IR &ir, int si, std::vector<uint32_t> &out) {
+    const SNode &s = ir.s[si];
+    out.push_back(s.kind);
+    switch (s.kind) {
+    case B_ACC:
+        out.push_back(s.mode | s.array << 1);
+        enc_block(ir, s.e, out);
+        break;
+    case B_SEQ:
+        out.push_back((uint32_t)s.kids.size());
+        for (int k : s.kids) enc_stmt(ir, k, out);
+        break;
+    case B_IF:
+        enc_block(ir, s.e, out);
+        enc_stmt(ir, s.kids[0], out);
+        enc_stmt(ir, s.kids[1], out);
+        break;
+    case B_FORU: case B_FORS:
+        out.push_back(s.slot);
+        enc_block(ir, s.lo, out);
+        enc_block(ir, s.hi, out);
+        enc_stmt(ir, s.kids[0], out);
+        break;
+    default: break;   // skip, sync
+    }
+}
+
+}  // namespace
+
+void encode(const IR &ir, std::vector<uint32_t> &out) {
+    std::vector<uint32_t> body;
+    if (ir.root >= 0) enc_stmt(ir, ir.root, body);
+    out.clear();
+    out.push_back(DRF_MAGIC);
+    out.push_back(1);
+    out.push_back(ir.nslots);
+    out.push_back((uint32_t)body.size());
+    out.insert(out.end(), body.begin(), body.end());
+}
+
+uint32_t ir_arrays(const IR &ir) {
+    uint32_t a = 0;
+    for (const SNode &s : ir.s)
+        if (s.kind == B_ACC && s.array > a) a = s.array;
+    return a + 1;
+}
+
+void ir_project(IR &ir, uint32_t array) {
+    for (SNode &s : ir.s) {
+        if (s.kind != B_ACC) continue;
+        if (s.array == array) {
+            s.array = 0;
+        } else {
+            s.kind = B_SKIP;
+            s.e = -1;
+        }
+    }
+}
+
+bool ir_bind(IR &ir, uint32_t slot, uint64_t v) {
+    for (const SNode &s : ir.s)
+        if ((s.kind == B_FORU || s.kind == B_FORS) && s.slot == slot) return false;
+    for (XNode &x : ir.x)
+        if (x.op == B_VAR && x.slot == slot) {
+            x.op = v < (1ull << 32) ? B_CONST32 : B_CONST64;
+            x.val = v;
+        }
+    return true;
 }
 
 }  // namespace drf

@@ -31,6 +31,7 @@ struct XNode {          // expression node
 struct SNode {          // statement node
     uint32_t kind;      // B_SKIP .. B_FORS
     uint32_t mode = 0;  // B_ACC: 0 read, 1 write
+    uint32_t array = 0; // B_ACC: shared array accessed (0 in a one-array protocol)
     uint32_t slot = 0;  // loops
     int e = -1;         // B_ACC index / B_IF condition
     int lo = -1, hi = -1;
@@ -78,9 +79,32 @@ struct Plan {
     std::vector<int> leaf_cal;         // per leaf code: offset of its compiled access leaf, or -1
 };
 
+// Arrays of one access word: bit 0 write, bits 1.. the array id.
+constexpr uint32_t MAX_ARRAYS = 1u << 16;
+
 int compile_text(const char *text, size_t len, std::vector<uint32_t> &out);
+// Slot the text compiler gives `name` (names get slots in order of first
+// appearance); -1 when the text does not mention it or does not compile.
+int text_slot(const char *text, size_t len, const char *name);
 int decode(const uint32_t *code, uint32_t words, IR &ir);     // 0 or E_BYTECODE
 int static_check(const IR &ir);                               // first violation or 0
 int plan_protocol(const uint32_t *code, uint32_t words, uint32_t n, Plan &plan);
+
+// Memory access protocol (text form) of a BabyCUDA program under the
+// typing context {tid} + params (space-separated names, may be null):
+// 0, a typing status (DRF_E_ILLTYPED, DRF_E_UNBOUND, DRF_E_SHADOW) or
+// DRF_E_ARG when the text is not a BabyCUDA program.
+int babycuda_infer(const char *text, size_t len, const char *params, std::string &map_text);
+
+// Bytecode of a decoded protocol (the inverse of decode).
+void encode(const IR &ir, std::vector<uint32_t> &out);
+// Arrays a protocol accesses: 1 + the largest array id (1 without accesses).
+uint32_t ir_arrays(const IR &ir);
+// The protocol of one array: its accesses become array-0 accesses, every
+// access to another array becomes skip (one protocol per array).
+void ir_project(IR &ir, uint32_t array);
+// Replaces every occurrence of variable `slot` by the constant v; false
+// when a loop binds the slot (it is then not a free parameter).
+bool ir_bind(IR &ir, uint32_t slot, uint64_t v);
 
 }  // namespace drf

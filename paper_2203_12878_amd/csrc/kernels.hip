@@ -1734,7 +1734,13 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             __syncthreads();
             uint32_t cnt = fast ? off : lds_n;
             total += cnt;
-            if (cnt > (uint32_t)TILE) cnt = TILE;   // cannot happen: bounded by count or plan
+            if (cnt > (uint32_t)TILE) {
+                // more events than the count or the plan bounded: the records
+                // past the tile were dropped, so the protocol gets an error
+                // status instead of a verdict
+                if (threadIdx.x == 0) atomicOr(&ovf_flags[u.proto], OVF_LIMIT);
+                cnt = TILE;
+            }
             if (cnt == 0) {
                 __syncthreads();
                 continue;
@@ -1766,7 +1772,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             __syncthreads();
             if (threadIdx.x == 0) {
                 atomicAdd(&nrec[u.proto], total);
-                if (lds_ovf) atomicOr(&ovf_flags[u.proto], 1u);
+                if (lds_ovf) atomicOr(&ovf_flags[u.proto], OVF_RANGE);
             }
         }
         __syncthreads();
@@ -1931,18 +1937,6 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
     }
 }
 
-// starts[sbase + d] = first output position of digit d of segment s
-// (the end of the last digit is the end of the segment's output).
-__global__ void k_starts(const Seg *__restrict__ segs, uint32_t nsegs, const unsigned long long *__restrict__ offs,
-                         unsigned long long *__restrict__ starts) {
-    const uint32_t s = blockIdx.x;
-    if (s >= nsegs) return;
-    const Seg sg = segs[s];
-    const uint32_t nd = 1u << sg.dbits;
-    for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x)
-        starts[(uint64_t)sg.sbase + d] = offs[sg.hbase + (uint64_t)d * sg.nchunks];
-}
-
 // ================================================================== tiles
 // Tile records are read straight into registers (all loads issued before
 // any use; lanes past the end re-read the last record, so no branch sits
@@ -2058,8 +2052,9 @@ __global__ void k_result(uint32_t count, const ResultIn *__restrict__ rin, const
     ResultIn r = rin[i];
     if (r.flags & RESULT_FROM_DEVICE) {
         r.num_records = nrec[i];
-        if (ovf_flags[i]) r.status = -7;   // range overflow found while evaluating
+        if (ovf_flags[i] & OVF_RANGE) r.status = -7;   // range overflow found while evaluating
     }
+    if (r.status == 0 && (ovf_flags[i] & OVF_LIMIT)) r.status = -10;
     drf_result_dev o;
     o.status = r.status;
     o.racy = 0;
@@ -2104,43 +2099,6 @@ __global__ void k_fill_multi(FillList L) {
 __global__ void k_init_acc(SingleAcc *__restrict__ a, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = SingleAcc{NONE32, NONE32, 0u, NONE32};
-}
-
-// ================================================================== scan
-// Exclusive scan of u64 in place: block sums, recursive scan of the sums,
-// then add.  1024 elements per block (256 threads x 4).
-constexpr uint32_t SCAN_PER = 1024;
-
-__global__ __launch_bounds__(256) void k_scan_block(unsigned long long *__restrict__ d, uint64_t n,
-                                                    unsigned long long *__restrict__ sums) {
-    __shared__ unsigned long long s[256];
-    const uint64_t base = (uint64_t)blockIdx.x * SCAN_PER + threadIdx.x * 4;
-    unsigned long long v[4];
-    unsigned long long tot = 0;
-    for (int j = 0; j < 4; j++) { v[j] = (base + j < n) ? d[base + j] : 0; tot += v[j]; }
-    s[threadIdx.x] = tot;
-    __syncthreads();
-    for (uint32_t o = 1; o < 256; o <<= 1) {
-        unsigned long long x = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
-        __syncthreads();
-        s[threadIdx.x] += x;
-        __syncthreads();
-    }
-    unsigned long long run = s[threadIdx.x] - tot;   // exclusive prefix of this thread
-    for (int j = 0; j < 4; j++) {
-        if (base + j < n) d[base + j] = run;
-        run += v[j];
-    }
-    if (threadIdx.x == 255 && sums) sums[blockIdx.x] = s[255];
-}
-
-__global__ void k_scan_add(unsigned long long *__restrict__ d, uint64_t n, const unsigned long long *__restrict__ sums) {
-    const uint64_t i = (uint64_t)blockIdx.x * SCAN_PER + threadIdx.x;
-    const unsigned long long add = sums[blockIdx.x];
-    for (int j = 0; j < 4; j++) {
-        const uint64_t k = i + (uint64_t)j * 256;
-        if (k < n) d[k] += add;
-    }
 }
 
 // ============================================================== wrappers
@@ -2191,26 +2149,6 @@ hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, c
     return launch(k_hist, dim3(nchunks), dim3(WG), s, segs, chunks, in, hist);
 }
 
-uint64_t scan_tmp_words(uint64_t n) {
-    uint64_t t = 0;
-    while (n > SCAN_PER) {
-        n = (n + SCAN_PER - 1) / SCAN_PER;
-        t += n;
-    }
-    return t + 1;
-}
-
-hipError_t launch_scan_u64(unsigned long long *data, uint64_t n, unsigned long long *tmp, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const uint64_t nb = (n + SCAN_PER - 1) / SCAN_PER;
-    if (nb == 1) return launch(k_scan_block, dim3(1), dim3(256), s, data, n, (unsigned long long *)nullptr);
-    hipError_t e = launch(k_scan_block, dim3((uint32_t)nb), dim3(256), s, data, n, tmp);
-    if (e != hipSuccess) return e;
-    e = launch_scan_u64(tmp, nb, tmp + nb, s);
-    if (e != hipSuccess) return e;
-    return launch(k_scan_add, dim3((uint32_t)nb), dim3(256), s, data, n, (const unsigned long long *)tmp);
-}
-
 hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
                           const unsigned long long *offs, unsigned long long *out, unsigned long long cap,
                           hipStream_t s) {
@@ -2220,11 +2158,6 @@ hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks
 hipError_t launch_offsets(const Seg *segs, uint32_t nsegs, unsigned long long *hist, unsigned long long *starts,
                           hipStream_t s) {
     return launch(k_offsets, dim3(nsegs), dim3(WG), s, segs, nsegs, hist, starts);
-}
-
-hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs, unsigned long long *starts,
-                         hipStream_t s) {
-    return launch(k_starts, dim3(nsegs), dim3(256), s, segs, nsegs, offs, starts);
 }
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands, Best *best,

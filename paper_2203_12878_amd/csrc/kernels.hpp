@@ -79,17 +79,12 @@ hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, boo
 hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
                        unsigned long long *hist, hipStream_t s);
 
-hipError_t launch_scan_u64(unsigned long long *data, uint64_t n, unsigned long long *tmp, hipStream_t s);
 hipError_t launch_offsets(const Seg *segs, uint32_t nsegs, unsigned long long *hist, unsigned long long *starts,
                           hipStream_t s);
-uint64_t scan_tmp_words(uint64_t n);
 
 hipError_t launch_scatter(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
                           const unsigned long long *offs, unsigned long long *out, unsigned long long cap,
                           hipStream_t s);
-
-hipError_t launch_starts(const Seg *segs, uint32_t nsegs, const unsigned long long *offs,
-                         unsigned long long *starts, hipStream_t s);
 
 hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long long *recs, Cand *cands,
                         Best *best, hipStream_t s);
@@ -123,6 +118,9 @@ struct drf_result_dev {
 };
 
 constexpr uint32_t RESULT_FROM_DEVICE = 1;   // record total and overflow come from the fused path
+// per-protocol flags set on the device
+constexpr uint32_t OVF_RANGE = 1;   // an evaluated value reached 2^63 or an index 2^32
+constexpr uint32_t OVF_LIMIT = 2;   // a fused group held more events than its bound
 
 struct ResultIn {
     int32_t status;

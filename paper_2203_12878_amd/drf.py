@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libdrf.so")
 
 OK = 0
 E_ARG, E_BYTECODE, E_UNBOUND, E_SHADOW, E_SYNC_IN_U = -1, -2, -3, -4, -5
-E_DIVERGENT, E_RANGE, E_NOMEM, E_HIP, E_LIMIT = -6, -7, -8, -9, -10
+E_DIVERGENT, E_RANGE, E_NOMEM, E_HIP, E_LIMIT, E_MULTI, E_ILLTYPED = -6, -7, -8, -9, -10, -11, -12
 NONE = 0xFFFFFFFF
 
 
@@ -35,7 +35,7 @@ class DrfError(RuntimeError):
 class Plan(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("num_phases", ctypes.c_uint32), ("index_bits", ctypes.c_uint32),
                 ("wide", ctypes.c_uint32), ("max_records", ctypes.c_uint64), ("nests", ctypes.c_uint64),
-                ("max_phase_records", ctypes.c_uint64)]
+                ("max_phase_records", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):
@@ -63,13 +63,20 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libdrf.so is not built (run paper_2203_12878_amd/build.py)")
+        # PyTorch ships its own HIP runtime under the same soname: loading it
+        # first makes libdrf bind to that one copy, so that device memory,
+        # streams and the library's launches share one runtime (a second
+        # copy loaded later could not open the device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         u32p = ctypes.POINTER(ctypes.c_uint32)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.drf_version.restype = ctypes.c_char_p
         L.drf_compile_text.argtypes = [ctypes.c_char_p, ctypes.c_size_t, u32p, ctypes.c_uint32, u32p]
         L.drf_plan_protocol.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Plan)]
+        L.drf_plan_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.POINTER(Plan), u64p]
         L.drf_ctx_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]
+        L.drf_ctx_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.drf_ctx_destroy.argtypes = [ctypes.c_void_p]
         L.drf_check_protocol.argtypes = [ctypes.c_void_p, u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
@@ -84,10 +91,31 @@ def lib() -> ctypes.CDLL:
         L.drf_prepared_launches.restype = ctypes.c_uint64
         for f in ("drf_prepare_batch", "drf_run_prepared", "drf_prepared_destroy"):
             getattr(L, f).restype = ctypes.c_int
+        L.drf_babycuda_infer.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_char_p,
+                                         ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_int32)]
+        L.drf_babycuda_infer.restype = ctypes.c_int
+        L.drf_text_slot.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_char_p, u32p]
+        L.drf_bind_param.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, u32p, ctypes.c_uint32,
+                                     u32p]
+        L.drf_plan_sweep.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.POINTER(Plan), u64p]
+        L.drf_check_sweep.argtypes = [ctypes.c_void_p, u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_uint64, ctypes.c_void_p]
+        L.drf_protocol_arrays.argtypes = [u32p, ctypes.c_uint32, u32p]
+        L.drf_plan_arrays.argtypes = [u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(Plan), ctypes.c_uint32,
+                                      u64p]
+        L.drf_check_arrays.argtypes = [ctypes.c_void_p, u32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        for f in ("drf_text_slot", "drf_bind_param", "drf_plan_sweep", "drf_check_sweep", "drf_protocol_arrays",
+                  "drf_plan_arrays", "drf_check_arrays"):
+            getattr(L, f).restype = ctypes.c_int
         L.drf_ctx_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
         L.drf_ctx_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
         L.drf_ctx_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        for f in ("drf_compile_text", "drf_plan_protocol", "drf_ctx_create", "drf_ctx_destroy",
+        for f in ("drf_compile_text", "drf_plan_protocol", "drf_plan_batch", "drf_ctx_create", "drf_ctx_release",
+                  "drf_ctx_destroy",
                   "drf_check_protocol", "drf_check_batch", "drf_ctx_set_tuning", "drf_ctx_get_tuning",
                   "drf_ctx_set_profiling"):
             getattr(L, f).restype = ctypes.c_int
@@ -119,6 +147,62 @@ def compile_text(text: str) -> np.ndarray:
     return out[:n.value].copy()
 
 
+def _code(c: Union[str, np.ndarray]) -> np.ndarray:
+    return compile_text(c) if isinstance(c, str) else np.ascontiguousarray(c, dtype=np.uint32)
+
+
+def infer(program: str, params: Sequence[str] = ()) -> Tuple[int, Optional[str]]:
+    """BabyCUDA program -> (status, protocol text): drf_babycuda_infer with
+    the typing context {tid} + params.  status 0 gives the protocol; else
+    E_ILLTYPED / E_UNBOUND / E_SHADOW and None."""
+    b = program.encode()
+    ps = " ".join(params).encode() if params else None
+    need = ctypes.c_size_t(0)
+    st = ctypes.c_int32(0)
+    cap = 4 * len(b) + 64
+    out = ctypes.create_string_buffer(cap)
+    rc = lib().drf_babycuda_infer(b, len(b), ps, out, cap, ctypes.byref(need), ctypes.byref(st))
+    if rc == E_NOMEM:
+        out = ctypes.create_string_buffer(need.value)
+        rc = lib().drf_babycuda_infer(b, len(b), ps, out, need.value, ctypes.byref(need), ctypes.byref(st))
+    if rc != OK:
+        raise DrfError(rc, "drf_babycuda_infer")
+    return (st.value, out.value.decode() if st.value == 0 else None)
+
+
+def text_slot(text: str, name: str) -> int:
+    """Variable slot of `name` in the bytecode compile_text(text) gives."""
+    b = text.encode()
+    s = ctypes.c_uint32(0)
+    rc = lib().drf_text_slot(b, len(b), name.encode(), ctypes.byref(s))
+    if rc != OK:
+        raise DrfError(rc, "drf_text_slot")
+    return s.value
+
+
+def bind_param(code: Union[str, np.ndarray], slot: int, value: int) -> np.ndarray:
+    """Bytecode with variable `slot` replaced by the constant `value`."""
+    c = _code(code)
+    n = ctypes.c_uint32(0)
+    out = np.zeros(len(c) + 64, dtype=np.uint32)
+    rc = lib().drf_bind_param(_u32p(c), len(c), slot, value, _u32p(out), len(out), ctypes.byref(n))
+    if rc == E_NOMEM:
+        out = np.zeros(n.value, dtype=np.uint32)
+        rc = lib().drf_bind_param(_u32p(c), len(c), slot, value, _u32p(out), len(out), ctypes.byref(n))
+    if rc != OK:
+        raise DrfError(rc, "drf_bind_param")
+    return out[:n.value].copy()
+
+
+def protocol_arrays(code: Union[str, np.ndarray]) -> int:
+    c = _code(code)
+    k = ctypes.c_uint32(0)
+    rc = lib().drf_protocol_arrays(_u32p(c), len(c), ctypes.byref(k))
+    if rc != OK:
+        raise DrfError(rc, "drf_protocol_arrays")
+    return k.value
+
+
 def plan(code: Union[str, np.ndarray], n: int) -> Plan:
     code = compile_text(code) if isinstance(code, str) else np.ascontiguousarray(code, dtype=np.uint32)
     p = Plan()
@@ -126,6 +210,30 @@ def plan(code: Union[str, np.ndarray], n: int) -> Plan:
     if rc != OK:
         raise DrfError(rc, "drf_plan_protocol")
     return p
+
+
+def pack(codes: Sequence[np.ndarray]):
+    """Concatenated bytecode and the offsets (count + 1) of each protocol."""
+    off = np.zeros(len(codes) + 1, dtype=np.uint64)
+    if codes:
+        off[1:] = np.cumsum([len(c) for c in codes])
+    code = np.concatenate(codes).astype(np.uint32) if codes else np.zeros(1, np.uint32)
+    return code, off
+
+
+def plan_batch(items: Sequence[Tuple[Union[str, np.ndarray], int]], checker: "Optional[Checker]" = None):
+    """drf_plan_batch: the plan of every protocol and the device scratch one
+    batched check of all of them may take (for the checker's tuning)."""
+    codes = [compile_text(c) if isinstance(c, str) else np.ascontiguousarray(c, dtype=np.uint32) for c, _ in items]
+    code, off = pack(codes)
+    nth = np.array([int(n) for _, n in items], dtype=np.uint32)
+    plans = (Plan * max(1, len(items)))()
+    total = np.zeros(1, dtype=np.uint64)
+    ctx = checker._ctx if checker is not None else None
+    rc = lib().drf_plan_batch(ctx, _u32p(code), _u64p(off), _u32p(nth), len(items), plans, _u64p(total))
+    if rc != OK:
+        raise DrfError(rc, "drf_plan_batch")
+    return list(plans)[:len(items)], int(total[0])
 
 
 @dataclass
@@ -151,10 +259,7 @@ class Batch:
                  for c, _ in items]
         self.count = len(items)
         self.nthreads = np.array([int(n) for _, n in items], dtype=np.uint32)
-        self.code_off = np.zeros(self.count + 1, dtype=np.uint64)
-        if codes:
-            self.code_off[1:] = np.cumsum([len(c) for c in codes])
-        self.code = np.concatenate(codes).astype(np.uint32) if codes else np.zeros(1, np.uint32)
+        self.code, self.code_off = pack(codes)
         self.plans = list(plans) if plans is not None else [plan(c, int(n)) for c, n in zip(codes, self.nthreads)]
         self.phase_off = np.zeros(self.count + 1, dtype=np.uint64)
         nph = [p.num_phases if p.status == 0 else 0 for p in self.plans]
@@ -167,20 +272,44 @@ class Batch:
 
     def collect(self) -> List[CheckResult]:
         """Copy results back (after the stream work has finished)."""
-        res = np.frombuffer(self.results.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[:self.count]
-        counts = self.counts.cpu().numpy().view(np.uint64)
-        out = []
-        for i in range(self.count):
-            r = res[i]
-            st = int(r["status"])
-            if st != 0:
-                out.append(CheckResult(st))
-                continue
-            wit = (int(r["phase"]), int(r["index"]), int(r["tid_i"]), int(r["tid_j"])) if r["racy"] else None
-            a = int(self.phase_off[i])
-            pc = counts[a:a + int(r["num_phases"])]   # a view: no per-phase Python objects
-            out.append(CheckResult(0, int(r["racy"]), wit, pc, int(r["num_records"])))
-        return out
+        return _collect(self.results, self.counts, self.phase_off, self.count)
+
+
+class Outputs:
+    """Device result and phase-count buffers for `count` results laid out
+    by their plans (as drf_check_batch lays them out)."""
+
+    def __init__(self, plans: Sequence[Plan], device: int = 0):
+        import torch
+        self.count = len(plans)
+        self.phase_off = np.zeros(self.count + 1, dtype=np.uint64)
+        nph = [p.num_phases if p.status == 0 else 0 for p in plans]
+        if nph:
+            self.phase_off[1:] = np.cumsum(nph)
+        self.total_phases = int(self.phase_off[-1])
+        dev = torch.device("cuda", device)
+        self.results = torch.zeros(max(1, self.count) * 40, dtype=torch.uint8, device=dev)
+        self.counts = torch.zeros(max(1, self.total_phases), dtype=torch.int64, device=dev)
+
+    def collect(self) -> List[CheckResult]:
+        return _collect(self.results, self.counts, self.phase_off, self.count)
+
+
+def _collect(results, counts_t, phase_off, count) -> List[CheckResult]:
+    res = np.frombuffer(results.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[:count]
+    counts = counts_t.cpu().numpy().view(np.uint64)
+    out = []
+    for i in range(count):
+        r = res[i]
+        st = int(r["status"])
+        if st != 0:
+            out.append(CheckResult(st))
+            continue
+        wit = (int(r["phase"]), int(r["index"]), int(r["tid_i"]), int(r["tid_j"])) if r["racy"] else None
+        a = int(phase_off[i])
+        pc = counts[a:a + int(r["num_phases"])]   # a view: no per-phase Python objects
+        out.append(CheckResult(0, int(r["racy"]), wit, pc, int(r["num_records"])))
+    return out
 
 
 class Prepared:
@@ -242,6 +371,12 @@ class Checker:
         except Exception:
             pass
 
+    def release(self, keep_bytes: int = 0) -> None:
+        """Hand the context's scratch pools back when they exceed keep_bytes."""
+        rc = lib().drf_ctx_release(self._ctx, int(keep_bytes))
+        if rc != OK:
+            raise DrfError(rc, "drf_ctx_release")
+
     def set_tuning(self, tile_events=0, digit_bits=0, unit_events=0, item_events=0):
         t = Tuning(tile_events, digit_bits, unit_events, item_events)
         rc = lib().drf_ctx_set_tuning(self._ctx, ctypes.byref(t))
@@ -282,6 +417,42 @@ class Checker:
                                       int(b.phase_off[i + 1] - b.phase_off[i]), s)
             if rc != OK:
                 raise DrfError(rc, "drf_check_protocol")
+
+    def check_sweep(self, proto: Union[str, np.ndarray], n: int, slot: int, first: int, count: int,
+                    stream=None) -> List[CheckResult]:
+        """drf_check_sweep: result i is that of the protocol with variable
+        `slot` bound to first + i (one batch)."""
+        import torch
+        c = _code(proto)
+        plans = (Plan * max(1, count))()
+        rc = lib().drf_plan_sweep(_u32p(c), len(c), n, slot, first, count, plans, None)
+        if rc != OK:
+            raise DrfError(rc, "drf_plan_sweep")
+        o = Outputs(list(plans)[:count], self.device)
+        rc = lib().drf_check_sweep(self._ctx, _u32p(c), len(c), n, slot, first, count,
+                                   ctypes.c_void_p(o.results.data_ptr()), ctypes.c_void_p(o.counts.data_ptr()),
+                                   o.total_phases, self._stream(stream))
+        if rc != OK:
+            raise DrfError(rc, "drf_check_sweep")
+        (stream or torch.cuda.current_stream(self.device)).synchronize()
+        return o.collect()
+
+    def check_arrays(self, proto: Union[str, np.ndarray], n: int, stream=None) -> List[CheckResult]:
+        """drf_check_arrays: one result per shared array the protocol accesses."""
+        import torch
+        c = _code(proto)
+        k = protocol_arrays(c)
+        plans = (Plan * k)()
+        rc = lib().drf_plan_arrays(_u32p(c), len(c), n, plans, k, None)
+        if rc != OK:
+            raise DrfError(rc, "drf_plan_arrays")
+        o = Outputs(list(plans), self.device)
+        rc = lib().drf_check_arrays(self._ctx, _u32p(c), len(c), n, ctypes.c_void_p(o.results.data_ptr()),
+                                    ctypes.c_void_p(o.counts.data_ptr()), o.total_phases, self._stream(stream))
+        if rc != OK:
+            raise DrfError(rc, "drf_check_arrays")
+        (stream or torch.cuda.current_stream(self.device)).synchronize()
+        return o.collect()
 
     def prepare(self, b: Batch, stream=None) -> Prepared:
         """Check `b` once and capture the device work as one hipGraph."""

@@ -1,14 +1,27 @@
 """Continuous-batching check server on one GPU.
 
 Requests (protocol text or bytecode, thread count) are compiled and planned
-on arrival (host-only library calls) to get their device footprint, then
-wait in an admission queue.  Each worker thread owns a libdrf context and
-its own HIP stream; whenever a worker is free it takes every waiting
-request, in arrival order, whose footprint still fits its budget (at least
-one), and checks them as one batch.  Requests that arrive while batches
-run are admitted as soon as a worker frees up, and batches of different
-workers overlap on the device.  Results stay in device memory until the
-batch completes; latency is measured from submit() to the result.
+on arrival (host-only library calls).  The plan carries the library's upper
+bound on the device scratch a check of the request takes; the part of it
+beyond the fixed per-call cost is the request's footprint.  Requests wait
+in an admission queue.  Each worker thread owns a libdrf context and its
+own HIP stream.  Whenever a worker is free it takes waiting requests, in
+arrival order, while the batch's footprint (the per-call cost plus the
+requests' footprints) fits what is left of ONE device-wide budget shared by
+all workers; the batch holds its footprint until it completes, then the
+worker hands its context's pools back down to a small retained size.  So
+the scratch held on the device stays within the budget plus the retained
+pools.  A request too large for the budget runs alone once nothing else is
+in flight (the library then splits its big phases into waves under the
+context's limit).
+
+Requests that arrive while batches run are admitted as soon as memory and
+a worker free up, and batches of different workers overlap on the device.
+Results stay in device memory until the batch completes; latency is
+measured from submit() to the result.  A request whose future was
+cancelled before admission is dropped; submit() raises Overloaded when the
+queue already holds max_queue requests.  hold() pauses admission (for
+maintenance; requests keep queueing) until resume().
 
     with Server(workers=2) as srv:
         fut = srv.submit("(seq (wr tid) (sync) (rd (mod (+ tid 1) 64)))", 64)
@@ -27,18 +40,13 @@ import numpy as np
 
 from . import drf
 
-# HBM bytes per access event of a phase that goes through HBM (two record
-# buffers and partition metadata); phases within one LDS tile need none.
-BYTES_PER_EVENT = 20
-TILE_EVENTS = 8192
-BASE_FOOTPRINT = 4096
+# scratch a worker's context keeps between batches (pool A of a typical
+# batch: metadata and witness candidates)
+RETAIN_BYTES = 64 << 20
 
 
-def footprint(p: drf.Plan) -> int:
-    """Device bytes a request may need beyond its fixed metadata."""
-    if p.status != 0 or p.max_phase_records <= TILE_EVENTS:
-        return BASE_FOOTPRINT
-    return BASE_FOOTPRINT + BYTES_PER_EVENT * int(p.max_records)
+class Overloaded(RuntimeError):
+    """The admission queue is full."""
 
 
 @dataclass
@@ -46,7 +54,7 @@ class Request:
     code: np.ndarray
     n: int
     plan: drf.Plan
-    bytes: int
+    bytes: int                      # footprint beyond the per-call cost
     t_submit: float
     future: Future
     t_done: float = 0.0
@@ -55,10 +63,12 @@ class Request:
 @dataclass
 class Stats:
     completed: int = 0
+    cancelled: int = 0
+    rejected: int = 0
     records: int = 0
     batches: int = 0
-    max_batch_bytes: int = 0          # largest footprint of a batch of two or more requests
     max_batch_size: int = 0
+    max_in_flight_bytes: int = 0      # largest sum of footprints held at once
     latencies: List[float] = field(default_factory=list)
 
     def percentile(self, q: float) -> float:
@@ -67,22 +77,50 @@ class Stats:
         return float(np.percentile(np.array(self.latencies), q))
 
 
+def admit(queue: Sequence[Request], call_bytes: int, free_bytes: int, in_flight: int,
+          max_batch: int) -> int:
+    """How many requests from the head of `queue` one batch takes.
+
+    Requests join in arrival order while the per-call cost plus their
+    footprints fits `free_bytes`.  When even the head request does not fit:
+    it runs alone if no batch is in flight (0 is returned only when the
+    queue is empty or the head must wait for memory)."""
+    if not queue:
+        return 0
+    used = call_bytes
+    k = 0
+    while k < len(queue) and k < max_batch and used + queue[k].bytes <= free_bytes:
+        used += queue[k].bytes
+        k += 1
+    if k == 0 and in_flight == 0:
+        k = 1
+    return k
+
+
 class Server:
     def __init__(self, device: int = 0, workers: int = 2, budget_bytes: int = 16 << 30,
-                 max_batch: int = 4096):
+                 max_batch: int = 4096, max_queue: int = 1 << 20):
         import torch
         self.device = device
-        self.budget = budget_bytes
+        self.budget = int(budget_bytes)
         self.max_batch = max_batch
+        self.max_queue = max_queue
         self.stats = Stats()
         self._q: deque = deque()
         self._cv = threading.Condition()
         self._stop = False
+        self._held = False
+        self._in_flight_bytes = 0
+        self._in_flight = 0
         self._threads = []
         self._checkers = []
         self._streams = []
+        # per-call scratch (what a check of the smallest protocol takes):
+        # charged once per batch, not per request
+        self.call_bytes = int(drf.plan("(skip)", 1).scratch_bytes)
         for w in range(workers):
-            chk = drf.Checker(device, scratch_limit=budget_bytes + (1 << 30))
+            # one batch may use the whole budget when it runs alone
+            chk = drf.Checker(device, scratch_limit=max(self.budget, 2 * self.call_bytes))
             self._checkers.append(chk)
             self._streams.append(torch.cuda.Stream(device=device))
         for w in range(workers):
@@ -96,13 +134,27 @@ class Server:
         code = drf.compile_text(proto) if isinstance(proto, str) else np.ascontiguousarray(proto, dtype=np.uint32)
         p = drf.plan(code, n)
         fut: Future = Future()
-        req = Request(code, int(n), p, footprint(p), t0, fut)
+        req = Request(code, int(n), p, max(0, int(p.scratch_bytes) - self.call_bytes), t0, fut)
         with self._cv:
             if self._stop:
                 raise RuntimeError("server is closed")
+            if len(self._q) >= self.max_queue:
+                self.stats.rejected += 1
+                raise Overloaded("admission queue holds %d requests" % len(self._q))
             self._q.append(req)
             self._cv.notify()
         return fut
+
+    def hold(self):
+        """Stop admitting new batches (batches in flight finish; requests
+        keep queueing up to max_queue)."""
+        with self._cv:
+            self._held = True
+
+    def resume(self):
+        with self._cv:
+            self._held = False
+            self._cv.notify_all()
 
     def reset_stats(self):
         """Start the statistics afresh (e.g. after a warm-up stream)."""
@@ -125,45 +177,73 @@ class Server:
         self.close()
 
     # -------------------------------------------------------------- worker
-    def _take(self) -> Optional[List[Request]]:
+    def _take(self) -> Optional[Tuple[List[Request], int]]:
         with self._cv:
-            while not self._q and not self._stop:
+            while True:
+                # requests cancelled while waiting are dropped
+                while self._q and self._q[0].future.cancelled():
+                    self._q.popleft()
+                    self.stats.cancelled += 1
+                if self._stop and not self._q:
+                    return None
+                if self._held and not self._stop:
+                    self._cv.wait()
+                    continue
+                k = admit(self._q, self.call_bytes, self.budget - self._in_flight_bytes, self._in_flight,
+                          self.max_batch)
+                if k:
+                    break
                 self._cv.wait()
-            if not self._q:
-                return None
-            batch = [self._q.popleft()]
-            used = batch[0].bytes
-            while self._q and len(batch) < self.max_batch and used + self._q[0].bytes <= self.budget:
+            batch = []
+            for _ in range(k):
                 r = self._q.popleft()
-                used += r.bytes
-                batch.append(r)
-            return batch
+                if r.future.set_running_or_notify_cancel():
+                    batch.append(r)
+                else:
+                    self.stats.cancelled += 1
+            held = min(self.budget, self.call_bytes + sum(r.bytes for r in batch)) if batch else 0
+            self._in_flight_bytes += held
+            self._in_flight += 1
+            st = self.stats
+            st.max_in_flight_bytes = max(st.max_in_flight_bytes, self._in_flight_bytes)
+            return batch, held
+
+    def _finish(self, held: int):
+        with self._cv:
+            self._in_flight_bytes -= held
+            self._in_flight -= 1
+            self._cv.notify_all()
 
     def _worker(self, w: int):
         import torch
         chk = self._checkers[w]
         stream = self._streams[w]
         while True:
-            batch = self._take()
-            if batch is None:
+            got = self._take()
+            if got is None:
                 return
+            batch, held = got
+            if not batch:
+                self._finish(held)
+                continue
             try:
                 with torch.cuda.stream(stream):
                     b = drf.Batch([(r.code, r.n) for r in batch], self.device, plans=[r.plan for r in batch])
                     chk.run_batch(b, stream)
                     stream.synchronize()
                     res = b.collect()
+                    chk.release(RETAIN_BYTES)
             except Exception as e:  # a failed batch fails its requests, not the server
+                self._finish(held)
                 for r in batch:
                     r.future.set_exception(e)
                 continue
+            self._finish(held)
             now = time.perf_counter()
             with self._cv:
                 st = self.stats
                 st.batches += 1
                 st.max_batch_size = max(st.max_batch_size, len(batch))
-                if len(batch) > 1:
-                    st.max_batch_bytes = max(st.max_batch_bytes, sum(r.bytes for r in batch))
                 for r, x in zip(batch, res):
                     r.t_done = now
                     st.completed += 1

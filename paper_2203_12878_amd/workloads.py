@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import itertools
 import math
+import re
 from typing import Iterator, List, Sequence, Tuple
 
 import numpy as np
@@ -238,6 +239,137 @@ def gen_tree_batch(batch_seed: int = 0, count: int = 2048, kmax: int = 20):
     """Tree-reduction batch: k uniform in 8..kmax, N = 2^k threads; in half
     of the instances the sync of one uniformly chosen level is removed."""
     return [_tree_instance(_rng(3, batch_seed, i), kmax) for i in range(count)]
+
+
+# ------------------------------------------------- several arrays, sweeps
+def gen_multi_array(seed: int = 0, count: int = 16, arrays: int = 3, max_threads: int = 512):
+    """Protocols over several shared arrays: mixed-batch shapes (thread
+    counts capped at max_threads) whose accesses are spread uniformly over
+    `arrays` named arrays A0.. (text form rd:Ak / wr:Ak).  Returns a list of
+    (text, n)."""
+    out = []
+    for i in range(count):
+        r = _rng(5, seed, i)
+        while True:
+            text, n, _ = _mixed_protocol(r)
+            if n <= max_threads:
+                break
+        parts = re.split(r"\((rd|wr) ", text)
+        acc_text = parts[0]
+        for j in range(1, len(parts), 2):
+            acc_text += "(%s:A%d %s" % (parts[j], int(r.integers(0, arrays)), parts[j + 1])
+        out.append((acc_text, n))
+    return out
+
+
+def gen_sweep_protocols():
+    """Parametric protocols (free parameter M) and the thread counts they
+    run with: the racy loop of the paper's Section 2, own / overlapping
+    slots of width M, M synchronized iterations (phases depend on M), and a
+    tree-like halving whose stride is M."""
+    return [
+        ("(foru x 0 M (seq (rd x) (wr x)))", 4),
+        ("(foru x 0 M (wr (+ (* tid M) x)))", 64),
+        ("(foru x 0 (+ M 1) (wr (+ (* tid M) x)))", 64),
+        ("(fors y 0 M (seq (wr (+ tid y)) (sync) (rd (mod (+ tid 1) 32))))", 32),
+        ("(if (< tid M) (seq (rd tid) (rd (+ tid M)) (wr tid)) (skip))", 256),
+        ("(seq (wr (* tid 3)) (if (< tid (- 64 M)) (rd (+ (* tid 3) (* 3 M))) (skip)))", 64),
+    ]
+
+
+# ------------------------------------------------------- BabyCUDA programs
+def gen_babycuda(seed: int, ill_typed: bool = False):
+    """A random BabyCUDA program (text form (skip) (sync) (wr n n')
+    (rd y n b) (seq ..) (if c b b) (for x n n b), rd:A / wr:A for a second
+    array), its thread count and parameter values.  Well typed unless
+    ill_typed: then one read-bound variable is used in an index, a guard or
+    a loop bound (a data-dependent access).  Returns (text, n, params)."""
+    r = _rng(6, seed, int(ill_typed))
+    n = int(r.integers(2, 7))
+    params = {"M": int(r.integers(0, 4))} if r.random() < 0.5 else {}
+    arrays = ["", "B"] if r.random() < 0.3 else [""]
+    fresh = itertools.count()
+    state = {"planted": False}
+
+    def pick(xs):
+        return xs[int(r.integers(0, len(xs)))]
+
+    def small(V):
+        terms = [int(r.integers(0, 4))]
+        for v in V:
+            if r.random() < 0.5:
+                terms.append(("*", int(r.integers(0, 3)), v))
+        return _sum(terms)
+
+    def index(V, D):
+        e = ("mod", small(V), int(r.integers(2, 7)))
+        if ill_typed and D and not state["planted"] and r.random() < 0.5:
+            state["planted"] = True
+            e = ("+", e, pick(D))
+        return e
+
+    def payload(V, D):
+        return _sum([int(r.integers(0, 9))] + [v for v in V + D if r.random() < 0.3])
+
+    def access(mode, arr):
+        return mode + (":" + arr if arr else "")
+
+    def block(V, D, depth):
+        k = r.random()
+        if depth >= 3 or k < 0.35:
+            if r.random() < 0.5 or not V:
+                return ("wr_", access("wr", pick(arrays)), index(V, D), payload(V, D))
+            y = "y%d" % next(fresh)
+            return ("rd_", access("rd", pick(arrays)), y, index(V, D), block(V, D + [y], depth + 1))
+        if k < 0.55:
+            y = "y%d" % next(fresh)
+            return ("rd_", access("rd", pick(arrays)), y, index(V, D), block(V, D + [y], depth + 1))
+        if k < 0.75:
+            c = (pick(["<", "<=", "=", "!=", ">", ">="]), small(V), small(V))
+            if ill_typed and D and not state["planted"] and r.random() < 0.5:
+                state["planted"] = True
+                c = ("<", pick(D), small(V))
+            return ("if", c, block(V, D, depth + 1), block(V, D, depth + 1))
+        if k < 0.9:
+            x = "x%d" % next(fresh)
+            hi = int(r.integers(0, 4))
+            hi_e = ("+", hi, pick(D)) if ill_typed and D and not state["planted"] and r.random() < 0.3 else hi
+            if hi_e is not hi:
+                state["planted"] = True
+            return ("for", x, 0, hi_e, block(V + [x], D, depth + 1))
+        return ("seq", block(V, D, depth + 1), block(V, D, depth + 1))
+
+    V0 = ["tid"] + list(params)
+    parts = []
+    for i in range(int(r.integers(1, 4))):
+        if r.random() < 0.3:
+            # a synchronized loop: its bounds are tid-free
+            x = "s%d" % next(fresh)
+            body = ("seq", block(V0[1:] + [x] + ["tid"], [], 1), ("sync",))
+            parts.append(("for", x, 0, int(r.integers(1, 3)), body))
+        else:
+            parts.append(block(V0, [], 0))
+        if r.random() < 0.6:
+            parts.append(("sync",))
+    if ill_typed and not state["planted"]:
+        parts.append(("rd_", "rd", "yz", 0, ("wr_", "wr", ("+", "yz", 1), 0)))
+
+    def text(b):
+        if isinstance(b, tuple) and b and b[0] == "wr_":
+            return "(%s %s %s)" % (b[1], to_text(b[2]), to_text(b[3]))
+        if isinstance(b, tuple) and b and b[0] == "rd_":
+            return "(%s %s %s %s)" % (b[1], b[2], to_text(b[3]), text(b[4]))
+        if isinstance(b, tuple) and b and b[0] == "if":
+            return "(if %s %s %s)" % (to_text(b[1]), text(b[2]), text(b[3]))
+        if isinstance(b, tuple) and b and b[0] == "for":
+            return "(for %s %s %s %s)" % (b[1], to_text(b[2]), to_text(b[3]), text(b[4]))
+        if isinstance(b, tuple) and b and b[0] == "seq":
+            return "(seq %s)" % " ".join(text(c) for c in b[1:])
+        if b == ("sync",):
+            return "(sync)"
+        raise AssertionError(b)
+
+    return "(seq %s)" % " ".join(text(p) for p in parts), n, params
 
 
 # ------------------------------------------------------------------ serving

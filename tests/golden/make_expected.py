@@ -3,7 +3,7 @@
 
 Calls only the CPU oracle (oracle/o2.c) on the seeded generators; the GPU
 tests and bench compare the HIP path against these files.  Usage:
-    python tests/golden/make_expected.py [small large large1 large2 tree mixed serve5k] [-j N]
+    python tests/golden/make_expected.py [small large large1 large2 tree mixed serve<R>k ...] [-j N]
 """
 import hashlib
 import json
@@ -33,9 +33,11 @@ def items_of(name):
         return [w.gen_large(int(name[5:]))], "gen_large(%d)" % int(name[5:])
     if name == "tree":
         return [(t, n) for t, n, _ in w.gen_tree_batch(0, 2048)], "gen_tree_batch(0, 2048)"
-    if name == "serve5k":
-        reqs = w.gen_requests(rate=5000.0, max_requests=1000, horizon_s=1.0)
-        return [(t, n) for _, t, n, _ in reqs], "gen_requests(rate=5000, max_requests=1000, horizon_s=1)"
+    if name.startswith("serve") and name.endswith("k") and name[5:-1].isdigit():
+        # 1000-request Poisson streams (the serving rows of the bench)
+        rate = 1000 * int(name[5:-1])
+        reqs = w.gen_requests(rate=float(rate), max_requests=1000, horizon_s=1.0)
+        return [(t, n) for _, t, n, _ in reqs], "gen_requests(rate=%d, max_requests=1000, horizon_s=1)" % rate
     if name == "mixed":
         return [(t, n) for t, n, _ in w.gen_mixed_batch(0, 4096)], "gen_mixed_batch(0, 4096)"
     raise SystemExit(name)

@@ -46,7 +46,7 @@ def test_bytecode_layout():
         d[j] = np.uint32(rng.integers(0, 2**32))
         p = drf.plan(d, 3)
         assert p.status in (0, drf.E_BYTECODE, drf.E_UNBOUND, drf.E_SHADOW, drf.E_SYNC_IN_U,
-                            drf.E_DIVERGENT, drf.E_RANGE, drf.E_LIMIT)
+                            drf.E_DIVERGENT, drf.E_RANGE, drf.E_LIMIT, drf.E_MULTI)
     p = drf.plan(c[:-1], 3)
     assert p.status == drf.E_BYTECODE
 
@@ -85,3 +85,29 @@ def test_plan_of_configs():
     for i in range(20):
         deep = "(foru v%d 0 1 %s)" % (i, deep)
     assert drf.plan(deep, 1).status == drf.E_LIMIT
+
+
+def test_plan_batch_agrees_with_plan_protocol():
+    items = [w.gen_small(0), w.gen_large(0), w.tree_protocol(12, None), ("(skip)", 1),
+             ("(fors x 0 tid (wr x))", 4), ("(wr (+ tid 1))", 70000)]
+    plans, total = drf.plan_batch(items)
+    singles = [drf.plan(t, n) for t, n in items]
+    fields = [f for f, _ in drf.Plan._fields_]
+    for a, b in zip(plans, singles):
+        assert [getattr(a, f) for f in fields] == [getattr(b, f) for f in fields]
+    call = drf.plan("(skip)", 1).scratch_bytes
+    # one call's cost once, plus every protocol's own part
+    assert max(p.scratch_bytes for p in singles) <= total <= sum(p.scratch_bytes for p in singles)
+    assert total >= call + 0.99 * sum(p.scratch_bytes - call for p in singles)
+    # big phases need record buffers: about 20 bytes per event of the large protocol
+    big = singles[1]
+    assert 16 * big.max_records <= big.scratch_bytes - call <= 24 * big.max_records
+    assert singles[0].scratch_bytes - call < (1 << 20)     # every phase fits one LDS tile
+
+
+def test_context_without_gpu_is_a_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p()
+    assert drf.lib().drf_ctx_create(0, 0, ctypes.byref(h)) == drf.E_HIP and not h.value

@@ -1,9 +1,9 @@
 """Prepared batches (one hipGraph per batch): every replay reproduces the
-direct check exactly, with eager checks and synchronizations between the
-replays; the autotuner's tunings keep results exact."""
-import numpy as np
+oracle's results exactly, with eager checks and synchronizations between
+the replays; the autotuner's tunings keep results equal to the oracle's."""
 import pytest
 
+from oracle import o2
 from paper_2203_12878_amd import workloads as w
 
 pytestmark = pytest.mark.gpu
@@ -18,12 +18,12 @@ def _items():
     return items
 
 
-def test_graph_replays_match_direct():
+def test_graph_replays_match_oracle():
     import torch
     from paper_2203_12878_amd import drf
     chk = drf.Checker(0)
     items = _items()
-    direct = chk.check_batch(items)
+    direct = o2.check_many(items, jobs=8)
     b = drf.Batch(items, 0)
     prep = chk.prepare(b)
     torch.cuda.synchronize()
@@ -48,9 +48,7 @@ def test_graph_replays_match_direct():
 def test_tunings_keep_results_exact(tune):
     from paper_2203_12878_amd import drf
     items = _items()
-    ref_chk = drf.Checker(0)
-    ref = ref_chk.check_batch(items)
-    ref_chk.close()
+    ref = o2.check_many(items, jobs=8)
     chk = drf.Checker(0)
     chk.set_tuning(**tune)
     got = chk.check_batch(items)
