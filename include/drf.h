@@ -224,6 +224,32 @@ int drf_check_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off
                     drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
                     void *stream);
 
+/* Allocation-free variant of drf_check_batch, for callers that cannot
+ * allocate device memory (code being captured into a HIP graph, tight
+ * serving loops, hosts that forbid it).  Same arguments, results, layout
+ * and per-protocol statuses as drf_check_batch.  It calls no hipMalloc,
+ * hipMallocAsync, hipHostMalloc or hipFree and grows no context pool: its
+ * device scratch is a fixed array of DRF_FIXED_SCRATCH_BYTES per device
+ * (part of the library's code object, held from load until the process
+ * ends; drf_ctx_create looks up its address), and its host staging and
+ * read-backs use ordinary host heap memory instead of pinned memory.
+ * Limits: the call's metadata (pool A) must fit the array, else the call
+ * returns DRF_E_NOMEM and writes nothing; the records of phases above one
+ * LDS tile use the rest of it, in waves, and a protocol with a single
+ * phase too large for that gets status DRF_E_NOMEM while the others are
+ * still checked.  Unlike the other checking calls it returns only after
+ * its work on `stream` has completed (its heap staging must outlive the
+ * copies).  Every allocation-free call on one device shares that device's
+ * array, which keeps the previous call's contents (the call clears what it
+ * needs): allocation-free calls that overlap on one device (other threads,
+ * other contexts or streams) race and must be serialized by the caller.
+ * Calls of the other entry points do not touch the array.  Profiling
+ * (drf_ctx_set_profiling) does not cover these calls. */
+#define DRF_FIXED_SCRATCH_BYTES (64ull << 20)
+int drf_check_batch_noalloc(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off,
+                            const uint32_t *nthreads, uint32_t count, drf_result *d_results,
+                            uint64_t *d_phase_counts, uint64_t phase_cap, void *stream);
+
 /* ---------------------------------------------------- parameter sweeps
  * A protocol may mention a free parameter (the racy example of Section 2
  * loops up to a symbolic M, typed under the context {M, tid} in Section 4).

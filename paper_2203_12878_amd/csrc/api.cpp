@@ -31,6 +31,7 @@
 #include <thread>
 #include <tuple>
 #include <initializer_list>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -39,6 +40,8 @@
 #include "kernels.hpp"
 
 using namespace drf;
+
+static_assert(FIXED_SCRATCH_BYTES == DRF_FIXED_SCRATCH_BYTES, "fixed scratch size of the C ABI");
 
 enum KClass { K_COUNT, K_FUSED, K_EMIT, K_HIST, K_SCAN, K_SCATTER, K_TILE, K_SINGLE, K_OTHER, K_NCLASS };
 static const char *KNAMES[K_NCLASS] = {"count", "fused", "emit", "hist", "scan", "scatter", "tile", "single", "other"};
@@ -62,6 +65,7 @@ struct drf_ctx {
     size_t pin_bi = 0, pin_off = 0;
     void *h_counts = nullptr;           // pinned read-back of per-phase counts and overflow flags
     size_t h_counts_cap = 0;
+    void *fixed = nullptr;              // the device's fixed scratch array (allocation-free calls)
     bool done_valid = false;
     uint32_t cus = 256;
     drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 15, 1u << 16};
@@ -195,8 +199,16 @@ void grow(drf_ctx *c, void *&p, size_t &size, size_t need, hipStream_t st) {
 // call's next stream sync.
 struct Keep {
     drf_ctx *ctx = nullptr;
+    // allocation-free calls stage on the host heap instead: blocks owned by
+    // the call, never reused within it, freed after its final stream sync
+    bool heap = false;
+    std::vector<std::unique_ptr<char[]>> heap_blocks;
     void *take(size_t bytes) {
         bytes = (bytes + 255) & ~(size_t)255;
+        if (heap) {
+            heap_blocks.emplace_back(new char[bytes]);
+            return heap_blocks.back().get();
+        }
         auto &B = ctx->pin_blocks;
         while (ctx->pin_bi < B.size() && ctx->pin_off + bytes > B[ctx->pin_bi].second) {
             ctx->pin_bi++;
@@ -223,6 +235,7 @@ struct Keep {
         return p;
     }
     void clear() {
+        if (heap) return;
         ctx->pin_bi = 0;
         ctx->pin_off = 0;
     }
@@ -289,6 +302,8 @@ struct Call {
     hipStream_t st;
     uint32_t count;
     Recorder *rec = nullptr;
+    bool noalloc = false;              // pools come from the fixed scratch array
+    void *A = nullptr, *B = nullptr;   // pool A / pool B of this call
     Trace tr;
 
     // run a device operation on the call's stream (and record it)
@@ -581,8 +596,8 @@ struct Wave {
 void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *best, Cand *cand) {
     drf_ctx *ctx = C.ctx;
     hipStream_t st = C.st;
-    void *A = ctx->poolA;
-    void *B = ctx->poolB;
+    void *A = C.A;
+    void *B = C.B;
     const size_t bi = W.bi, be = W.be;
     const uint64_t recs = W.recs;
     const uint64_t win_lo = big[bi].k;
@@ -733,35 +748,45 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
         // writes them straight into pinned host memory, and the host builds
         // the next tiles while the scatter runs.  A recorded call writes them
         // to device memory and copies them back (its replays must not write
-        // host memory that may since have been released).
-        if (nstarts * 8 > ctx->h_starts_cap) {
-            if (ctx->h_starts) hipck(hipHostFree(ctx->h_starts));
-            ctx->h_starts = nullptr;
-            ctx->h_starts_cap = 0;
-            const size_t want = std::max<size_t>(nstarts * 8, 8u << 20);
-            if (hipHostMalloc(&ctx->h_starts, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-                ctx->h_starts = nullptr;
-                (void)hipGetLastError();
-                throw Fail{DRF_E_NOMEM};
-            }
-            ctx->h_starts_cap = want;
-        }
-        const uint64_t *starts = (const uint64_t *)ctx->h_starts;
+        // host memory that may since have been released); so does an
+        // allocation-free call, into host heap memory, reading them once the
+        // stream has drained (it takes no pinned memory).
+        std::vector<uint64_t> heap_starts;
+        const uint64_t *starts = nullptr;
         unsigned long long *wstarts = dstarts;
-        if (!C.rec) hipck(hipHostGetDevicePointer((void **)&wstarts, ctx->h_starts, 0));
+        if (C.noalloc) {
+            heap_starts.resize(nstarts);
+            starts = heap_starts.data();
+        } else {
+            if (nstarts * 8 > ctx->h_starts_cap) {
+                if (ctx->h_starts) hipck(hipHostFree(ctx->h_starts));
+                ctx->h_starts = nullptr;
+                ctx->h_starts_cap = 0;
+                const size_t want = std::max<size_t>(nstarts * 8, 8u << 20);
+                if (hipHostMalloc(&ctx->h_starts, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+                    ctx->h_starts = nullptr;
+                    (void)hipGetLastError();
+                    throw Fail{DRF_E_NOMEM};
+                }
+                ctx->h_starts_cap = want;
+            }
+            starts = (const uint64_t *)ctx->h_starts;
+            if (!C.rec) hipck(hipHostGetDevicePointer((void **)&wstarts, ctx->h_starts, 0));
+        }
         {
             // counts in, output positions out (read twice, written once)
             Prof pr(ctx, st, K_SCAN, 0, hb * 24);
             C.dev([=](hipStream_t s) { return launch_offsets(dsegs, nsg, hist, wstarts, s); });
         }
         if (C.rec) hipck(hipMemcpyAsync(ctx->h_starts, dstarts, nstarts * 8, hipMemcpyDeviceToHost, st));
-        if (!ctx->parted) hipck(hipEventCreateWithFlags(&ctx->parted, hipEventDisableTiming));
+        if (C.noalloc) hipck(hipMemcpyAsync(heap_starts.data(), dstarts, nstarts * 8, hipMemcpyDeviceToHost, st));
         hipck(hipEventRecord(ctx->parted, st));
         {
             Prof pr(ctx, st, K_SCATTER, op, op * 16);
             C.dev([=](hipStream_t s) { return launch_scatter(dsegs, dch, nch, cin, hist, cout, recs, s); });
         }
-        hipck(hipEventSynchronize(ctx->parted));
+        if (C.noalloc) hipck(hipStreamSynchronize(st));
+        else hipck(hipEventSynchronize(ctx->parted));
         C.tr.mark("level partitioned", segs.size());
 
         std::vector<Seg> next;
@@ -820,17 +845,30 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     }
 }
 
+// Profiling off for the duration of one call (an allocation-free call
+// creates no timing events).
+struct ProfOff {
+    drf_ctx *c;
+    bool was;
+    explicit ProfOff(drf_ctx *ctx, bool on) : c(ctx), was(ctx->prof) { if (on) c->prof = false; }
+    ~ProfOff() { c->prof = was; }
+};
+
 int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
                uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
-               hipStream_t st, Recorder *rec = nullptr) {
+               hipStream_t st, Recorder *rec = nullptr, bool noalloc = false) {
     if (!ctx || !code_off || !nthreads || (count && (!code || !d_results))) return DRF_E_ARG;
     if (count == 0) return DRF_OK;
+    if (noalloc && (rec || !ctx->fixed)) return DRF_E_ARG;
     Call C;
     C.ctx = ctx;
     C.st = st;
     C.count = count;
     C.rec = rec;
+    C.noalloc = noalloc;
     C.keep.ctx = ctx;
+    C.keep.heap = noalloc;
+    ProfOff prof_off(ctx, noalloc);
     try {
         hipck(hipSetDevice(ctx->device));
         if (ctx->done_valid) hipck(hipStreamWaitEvent(st, ctx->done, 0));
@@ -847,8 +885,15 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         if (ctx->done_valid) hipck(hipEventSynchronize(ctx->done));
         prof_collect(ctx);
         C.keep.clear();
-        grow(ctx, ctx->poolA, ctx->sizeA, C.needA, st);
-        void *A = ctx->poolA;
+        if (noalloc) {
+            // pool A at the start of the fixed array, pool B after it
+            if (C.needA > FIXED_SCRATCH_BYTES) throw Fail{DRF_E_NOMEM};
+            C.A = ctx->fixed;
+        } else {
+            grow(ctx, ctx->poolA, ctx->sizeA, C.needA, st);
+            C.A = ctx->poolA;
+        }
+        void *A = C.A;
         unsigned long long *phase_counts = (unsigned long long *)d_phase_counts;
         Best *best = at<Best>(A, C.o_best);
         Cand *cand = at<Cand>(A, C.o_cand);
@@ -963,7 +1008,19 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         C.tr.mark("count launched");
         uint64_t *counts = nullptr;
         uint32_t *hovf = nullptr;
-        if (dynamic) {
+        std::vector<uint64_t> heap_counts;
+        std::vector<uint32_t> heap_ovf;
+        if (dynamic && noalloc) {
+            // host heap read-back, read once the stream has drained
+            heap_counts.resize(std::max<uint64_t>(1, C.total_phases));
+            heap_ovf.resize(count);
+            counts = heap_counts.data();
+            hovf = heap_ovf.data();
+            if (C.total_phases)
+                hipck(hipMemcpyAsync(counts, phase_counts, C.total_phases * sizeof(uint64_t),
+                                     hipMemcpyDeviceToHost, st));
+            hipck(hipMemcpyAsync(hovf, ovf, count * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        } else if (dynamic) {
             // pinned read-back buffers of the context (not the upload staging,
             // which a sync in between may recycle)
             const size_t need = (std::max<uint64_t>(1, C.total_phases) * sizeof(uint64_t) + 255) & ~(size_t)255;
@@ -985,7 +1042,6 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 hipck(hipMemcpyAsync(counts, phase_counts, C.total_phases * sizeof(uint64_t),
                                      hipMemcpyDeviceToHost, st));
             hipck(hipMemcpyAsync(hovf, ovf, count * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-            if (!ctx->counted) hipck(hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming));
             hipck(hipEventRecord(ctx->counted, st));
         }
 
@@ -1006,7 +1062,8 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         std::vector<Unit> units[2];
         std::vector<BigPhase> big;
         if (dynamic) {
-            hipck(hipEventSynchronize(ctx->counted));
+            if (noalloc) hipck(hipStreamSynchronize(st));
+            else hipck(hipEventSynchronize(ctx->counted));
             uint64_t dyn_events = 0;
             for (uint32_t i = 0; i < count; i++) {
                 if (C.status[i] || C.stat[i] || hovf[i]) continue;
@@ -1060,7 +1117,9 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
 
         // ---- big phases, in waves under the scratch budget
         if (!big.empty()) {
-            const uint64_t budget = ctx->limit > ctx->sizeA ? ctx->limit - ctx->sizeA : 0;
+            const uint64_t a_end = (C.needA + ALIGN - 1) & ~(ALIGN - 1);
+            const uint64_t budget = noalloc ? (FIXED_SCRATCH_BYTES > a_end ? FIXED_SCRATCH_BYTES - a_end : 0)
+                                            : (ctx->limit > ctx->sizeA ? ctx->limit - ctx->sizeA : 0);
             // records per wave: about 21 bytes of pool B per record (two
             // record buffers and the partition metadata); the cap shrinks
             // until the largest wave's layout fits the budget
@@ -1115,7 +1174,13 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 }
                 rec_cap = (uint64_t)((double)rec_cap * ((double)budget / (double)needB) * 0.98);
             }
-            grow(ctx, ctx->poolB, ctx->sizeB, needB, st);
+            if (noalloc) {
+                if (needB > budget) throw Fail{DRF_E_NOMEM};
+                C.B = (char *)ctx->fixed + a_end;
+            } else {
+                grow(ctx, ctx->poolB, ctx->sizeB, needB, st);
+                C.B = ctx->poolB;
+            }
             C.tr.mark("waves planned", waves.size());
             for (const Wave &W : waves) run_wave(C, big, W, best, cand);
             C.tr.mark("waves done");
@@ -1135,9 +1200,11 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             drf_result_dev *dres = (drf_result_dev *)d_results;
             C.dev([=](hipStream_t s) { return launch_result(count, drin, best, nrec_dev, ovf, dres, s); });
         }
-        if (!ctx->done) hipck(hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming));
         hipck(hipEventRecord(ctx->done, st));
         ctx->done_valid = true;
+        // an allocation-free call's staging lives on the host heap until
+        // this call returns: wait for the stream before releasing it
+        if (noalloc) hipck(hipStreamSynchronize(st));
         // every upload came from pinned staging that the context keeps until
         // its next call has waited for this event: return without waiting
         C.tr.mark("enqueued");
@@ -1183,6 +1250,14 @@ uint64_t scratch_estimate(const drf_ctx *tuned, std::vector<Plan> &&plans) {
         b = wave_layout(bigrec, nbig, nbig, C.items[0].size(), C.items[1].size(), tmp.tune.tile_events, small,
                         tmp.tune.digit_bits).bytes;
     return C.needA + b;
+}
+
+// The context's synchronization events, created up front so that no
+// checking call creates any.
+bool ctx_events(drf_ctx *c) {
+    return hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&c->counted, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&c->parted, hipEventDisableTiming) == hipSuccess;
 }
 
 void fill_plan(const Plan &p, drf_plan *out) {
@@ -1277,6 +1352,13 @@ int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out) 
         scratch_limit_bytes = fr / 4 * 3;
     }
     c->limit = scratch_limit_bytes;
+    // the fixed scratch array's address on this device (looked up once per
+    // device, with the device current) for allocation-free calls
+    if (!ctx_events(c) || fixed_scratch_address(hip_device, &c->fixed) != hipSuccess) {
+        (void)hipGetLastError();
+        drf_ctx_destroy(c);
+        return DRF_E_HIP;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
         c->cus = (uint32_t)cus;
@@ -1421,6 +1503,11 @@ int drf_prepare_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_o
     p->priv->tune = ctx->tune;
     p->priv->cus = ctx->cus;
     p->rec.limit = ctx->limit;
+    if (!ctx_events(p->priv)) {
+        (void)hipGetLastError();
+        drf_prepared_destroy(p);
+        return DRF_E_HIP;
+    }
     int rc = check_impl(p->priv, code, code_off, nthreads, count, d_results, d_phase_counts, phase_cap,
                         (hipStream_t)stream, &p->rec);
     if (rc != DRF_OK) {
@@ -1644,6 +1731,13 @@ int drf_check_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off
                     void *stream) {
     return check_impl(ctx, code, code_off, nthreads, count, d_results, d_phase_counts, phase_cap,
                       (hipStream_t)stream);
+}
+
+int drf_check_batch_noalloc(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                            uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
+                            void *stream) {
+    return check_impl(ctx, code, code_off, nthreads, count, d_results, d_phase_counts, phase_cap,
+                      (hipStream_t)stream, nullptr, true);
 }
 
 }  // extern "C"

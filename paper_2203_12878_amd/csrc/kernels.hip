@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace drf {
@@ -2211,6 +2213,37 @@ hipError_t launch_init_acc(SingleAcc *a, uint32_t n, hipStream_t s) {
 
 hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s) {
     return launch(k_pick, dim3((uint32_t)((ncands + 255) / 256)), dim3(256), s, cands, ncands, best);
+}
+
+// ------------------------------------------------ fixed scratch array
+// Scratch of the allocation-free checking call: one array per device, part
+// of the code object, so it exists from module load until the process
+// ends and no call allocates it.  Host code must not pass `scratch` itself
+// to a kernel (on the host the name is only a stand-in); it passes the
+// device address hipGetSymbolAddress returns with that device current.
+static __device__ __align__(256) unsigned char scratch[FIXED_SCRATCH_BYTES];
+
+constexpr int FIXED_MAX_DEVICES = 64;
+
+hipError_t fixed_scratch_address(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[FIXED_MAX_DEVICES] = {};
+    if (device < 0 || device >= FIXED_MAX_DEVICES || !ptr) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace drf

@@ -133,4 +133,12 @@ struct ResultIn {
 hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, const unsigned long long *nrec,
                          const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s);
 
+// Bytes of the per-device scratch array of the allocation-free checking
+// call (a file-scope device array in kernels.hip, held until the process
+// ends).
+constexpr uint64_t FIXED_SCRATCH_BYTES = 64ull << 20;   // DRF_FIXED_SCRATCH_BYTES of the C ABI
+// Device address of that array on `device` (looked up once per device with
+// the device current, then cached).
+hipError_t fixed_scratch_address(int device, void **ptr);
+
 }  // namespace drf

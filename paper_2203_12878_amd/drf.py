@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.drf_check_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.drf_check_batch_noalloc.argtypes = L.drf_check_batch.argtypes
+        L.drf_check_batch_noalloc.restype = ctypes.c_int
         L.drf_prepare_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_void_p)]
@@ -401,6 +403,17 @@ class Checker:
                                    b.total_phases, self._stream(stream))
         if rc != OK:
             raise DrfError(rc, "drf_check_batch")
+
+    def run_batch_noalloc(self, b: Batch, stream=None) -> None:
+        """drf_check_batch_noalloc for a prepared batch: the same check with
+        the library's fixed per-device scratch array instead of context
+        pools (returns once the work on the stream has completed)."""
+        rc = lib().drf_check_batch_noalloc(self._ctx, _u32p(b.code), _u64p(b.code_off), _u32p(b.nthreads), b.count,
+                                           ctypes.c_void_p(b.results.data_ptr()),
+                                           ctypes.c_void_p(b.counts.data_ptr()), b.total_phases,
+                                           self._stream(stream))
+        if rc != OK:
+            raise DrfError(rc, "drf_check_batch_noalloc")
 
     def run_plain(self, b: Batch, stream=None) -> None:
         """The plain path: drf_check_protocol once per protocol of the batch."""
