@@ -57,18 +57,24 @@ enum : uint32_t {
 // each lane then runs its short chain.  Layout (words, from cal_off):
 //   nacc nuni acc_off (offset of the first access block from cal_off)
 //   nuni x { len <postfix X_* code over loop variables> }
-//   nacc x { mode form c0 m0k m0 a us pk pa nops { opw arg } * nops }
+//   nacc x { mode form c0 m0k m0 a us pk pa m0mag m0sh pamag pash nops
+//            { opw arg } * nops }
 // opw = C_* | (C_UNI if arg is a uniform slot, else arg is the immediate).
 // form 1: the chain is ((tid + c0) m0-op m0) * a + U[us] then pk-op pa, with
 // op kinds CAL_K_NONE / CAL_K_AND / CAL_K_MOD, us NONE32 when there is no
-// uniform term (the same operations as the chain, in the same order);
-// form 0: only the chain applies.
+// uniform term (the same operations as the chain, in the same order).  A
+// modulus d of the fixed form is >= 1 (mod 0 is the identity: kind NONE)
+// and comes with the multiplier and shifts of exact division by the
+// invariant d (mag, sh1 | sh2 << 8: Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994, unsigned case):
+// x / d = (t + ((x - t) >> sh1)) >> sh2 with t = mulhi(mag, x), for every
+// 32-bit x.  form 0: only the chain applies.
 enum : uint32_t {
     C_ADD = 1, C_MUL, C_MONUS, C_RMONUS, C_DIV, C_MOD, C_SHL, C_SHR, C_MIN, C_MAX, C_AND,
     C_UNI = 0x100,
 };
 constexpr uint32_t CAL_K_NONE = 0, CAL_K_AND = 1, CAL_K_MOD = 2;
-constexpr uint32_t CAL_HDR = 10;     // words before an access's chain ops
+constexpr uint32_t CAL_HDR = 14;     // words before an access's chain ops
 constexpr uint32_t CAL_MAXU = 32;    // uniform slots of one leaf (a chunk then stages >= 64 iterations)
 constexpr uint32_t CAL_MAXOPS = 16;  // chain operations of one access
 

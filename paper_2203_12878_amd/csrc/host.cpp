@@ -13,6 +13,20 @@
 
 namespace drf {
 
+// Multiplier and shifts for exact unsigned division of 32-bit values by
+// the invariant d >= 1 (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994, unsigned case with N = 32):
+// l = ceil(log2 d), mag = floor(2^32 (2^l - d) / d) + 1, sh1 = min(l, 1),
+// sh2 = max(l - 1, 0); then x / d = (t + ((x - t) >> sh1)) >> sh2 with
+// t = floor(mag * x / 2^32).
+static void div_magic(uint32_t d, uint32_t &mag, uint32_t &sh) {
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) l++;
+    mag = (uint32_t)(((((1ull << l) - d) << 32) / d) + 1);
+    const uint32_t sh1 = l < 1 ? l : 1, sh2 = l > 0 ? l - 1 : 0;
+    sh = sh1 | (sh2 << 8);
+}
+
 typedef unsigned __int128 u128;
 static const u128 SAT = (u128)1 << 64;                 // saturation point of intervals
 static const uint64_t VALUE_LIMIT = 1ull << 63;
@@ -946,8 +960,9 @@ struct Planner {
         c[acc_at] = (uint32_t)(c.size() - (size_t)at);
         for (size_t j = 0; j < accs.size(); j++) {
             // the fixed form: [ADD c0] [AND|MOD m0] [MUL a] [ADD uniform] [AND|MOD pa]
-            // form c0 m0k m0 a us pk pa (mode before, nops after: CAL_HDR words in all)
-            uint32_t hdr[CAL_HDR - 2] = {0, 0, CAL_K_NONE, 0, 1, NONE32, CAL_K_NONE, 0};
+            // form c0 m0k m0 a us pk pa m0mag m0sh pamag pash (mode before,
+            // nops after: CAL_HDR words in all)
+            uint32_t hdr[CAL_HDR - 2] = {0, 0, CAL_K_NONE, 0, 1, NONE32, CAL_K_NONE, 0, 0, 0, 0, 0};
             size_t q = 0;
             const auto &e = enc[j];
             auto kind = [](uint32_t op) { return op == C_AND ? CAL_K_AND : op == C_MOD ? CAL_K_MOD : CAL_K_NONE; };
@@ -957,6 +972,15 @@ struct Planner {
             if (q < e.size() && e[q].first == (C_ADD | C_UNI)) { hdr[5] = e[q].second; q++; }
             if (q < e.size() && (e[q].first == C_AND || e[q].first == C_MOD)) { hdr[6] = kind(e[q].first); hdr[7] = e[q].second; q++; }
             hdr[0] = q == e.size() ? 1u : 0u;
+            // moduli of the fixed form: mod 0 is the identity, any other
+            // gets its division magic
+            for (int m = 0; m < 2; m++) {
+                uint32_t &k = hdr[m ? 6 : 2];
+                const uint32_t d = hdr[m ? 7 : 3];
+                if (k != CAL_K_MOD) continue;
+                if (d == 0) { k = CAL_K_NONE; continue; }
+                div_magic(d, hdr[m ? 10 : 8], hdr[m ? 11 : 9]);
+            }
             c.push_back(ir.s[accs[j]].mode);
             for (uint32_t w : hdr) c.push_back(w);
             c.push_back((uint32_t)e.size());

@@ -482,27 +482,35 @@ DEV uint32_t cal_chain(const uint32_t *__restrict__ ap, uint32_t nops, uint32_t 
     return v;
 }
 
+// One modulus step of a compiled access's fixed form: v & d, v mod d (the
+// quotient by the stored division magic of d >= 1, then the remainder) or
+// v unchanged.
+DEV uint32_t fixed_op(uint32_t v, uint32_t kind, uint32_t d, uint32_t mag, uint32_t sh) {
+    if (kind == CAL_K_AND) return v & d;
+    if (kind == CAL_K_MOD) {
+        const uint32_t t = __umulhi(mag, v);
+        const uint32_t q = (t + ((v - t) >> (sh & 0xFFu))) >> (sh >> 8);
+        return v - q * d;
+    }
+    return v;
+}
+
 // Index of one compiled access (block at ap) for tid: the fixed form with
 // its parameters read once, else the chain.
 DEV uint32_t cal_index(const uint32_t *__restrict__ ap, uint32_t tid, const uint32_t *U, uint32_t ustride) {
     if (rfl(ap[1]) == 1u) {
         const uint32_t c0 = rfl(ap[2]), m0k = rfl(ap[3]), m0 = rfl(ap[4]), a = rfl(ap[5]), us = rfl(ap[6]);
         const uint32_t pk = rfl(ap[7]), pa = rfl(ap[8]);
-        uint32_t v = tid + c0;
-        if (m0k == CAL_K_AND) v &= m0;
-        else if (m0k == CAL_K_MOD) v = m0 ? v % m0 : v;
-        v *= a;
+        uint32_t v = fixed_op(tid + c0, m0k, m0, rfl(ap[9]), rfl(ap[10])) * a;
         if (us != NONE32) v += rfl(U[us * ustride]);
-        if (pk == CAL_K_AND) v &= pa;
-        else if (pk == CAL_K_MOD) v = pa ? v % pa : v;
-        return v;
+        return fixed_op(v, pk, pa, rfl(ap[11]), rfl(ap[12]));
     }
     return cal_chain(ap + CAL_HDR, rfl(ap[CAL_HDR - 1]), tid, U, ustride);
 }
 
 // A compiled access's header read once (uniform), for several iterations.
 struct CalHdr {
-    uint32_t mode, form, c0, m0k, m0, a, us, pk, pa, nops;
+    uint32_t mode, form, c0, m0k, m0, a, us, pk, pa, m0mag, m0sh, pamag, pash, nops;
     const uint32_t *ops;
 };
 DEV CalHdr cal_hdr(const uint32_t *__restrict__ ap) {
@@ -516,20 +524,19 @@ DEV CalHdr cal_hdr(const uint32_t *__restrict__ ap) {
     h.us = rfl(ap[6]);
     h.pk = rfl(ap[7]);
     h.pa = rfl(ap[8]);
+    h.m0mag = rfl(ap[9]);
+    h.m0sh = rfl(ap[10]);
+    h.pamag = rfl(ap[11]);
+    h.pash = rfl(ap[12]);
     h.nops = rfl(ap[CAL_HDR - 1]);
     h.ops = ap + CAL_HDR;
     return h;
 }
 DEV uint32_t cal_eval(const CalHdr &h, uint32_t tid, const uint32_t *U, uint32_t ustride) {
     if (h.form == 1u) {
-        uint32_t v = tid + h.c0;
-        if (h.m0k == CAL_K_AND) v &= h.m0;
-        else if (h.m0k == CAL_K_MOD) v = h.m0 ? v % h.m0 : v;
-        v *= h.a;
+        uint32_t v = fixed_op(tid + h.c0, h.m0k, h.m0, h.m0mag, h.m0sh) * h.a;
         if (h.us != NONE32) v += rfl(U[h.us * ustride]);
-        if (h.pk == CAL_K_AND) v &= h.pa;
-        else if (h.pk == CAL_K_MOD) v = h.pa ? v % h.pa : v;
-        return v;
+        return fixed_op(v, h.pk, h.pa, h.pamag, h.pash);
     }
     return cal_chain(h.ops, h.nops, tid, U, ustride);
 }
@@ -1082,6 +1089,44 @@ static_assert((2 * TILE_LDS - SURV_WORDS) / 4 >= 2 * SURV_CAP, "no room for the 
 static_assert(RED_OVF >= 4 * (TWG / 64) && RED_OVF < RED_NC && RED_NC < RED_CAND,
               "reduction slots overlap");
 
+constexpr uint32_t HSLOTS_MAX = 4096;   // hash table slots at most
+static_assert(HSLOTS_MAX * 16 <= TILE_LDS * 8, "hash table exceeds the group LDS");
+
+constexpr uint32_t floor_log2(uint32_t x) { return x <= 1 ? 0 : 1 + floor_log2(x >> 1); }
+
+// Sizes of the decision's methods for a scratch array of LW u64 words (a
+// group of at most LW - LW / 33 records): table cells, filter bitmap bits,
+// compact survivors and hash table slots all scale with the scratch.
+template <uint32_t LW>
+struct Scratch {
+    static constexpr uint32_t words = 2 * LW;                                   // u32 words
+    static constexpr uint32_t tbl_cells = words / 3;                            // three u32 per cell
+    static constexpr uint32_t fbits = floor_log2(LW) + 5 < FILTER_BITS ? floor_log2(LW) + 5 : FILTER_BITS;
+    static constexpr uint32_t fwords = 1u << (fbits - 5);                       // each bitmap
+    static constexpr uint32_t surv_cap = (1u << floor_log2(words / 12)) < SURV_CAP ? (1u << floor_log2(words / 12))
+                                                                                   : SURV_CAP;
+    static constexpr uint32_t surv_words = 2 * (surv_cap + surv_cap / 32);
+    static constexpr uint32_t hslots = (1u << floor_log2(words / 4)) < HSLOTS_MAX ? (1u << floor_log2(words / 4))
+                                                                                  : HSLOTS_MAX;
+    static_assert(2 * fwords <= words, "filter bitmaps exceed the scratch");
+    static_assert(surv_words <= fwords, "compact survivors overlap the repeated bitmap");
+    static_assert((words - surv_words) / 4 >= 2 * surv_cap, "no room for the table above the survivors");
+    static_assert(hslots * 4 <= words, "hash table exceeds the scratch");
+};
+
+// One record's update of its cell's aggregate (least tid t0, least tid
+// other than t0 t1, least writing tid w0), in one pass over the records:
+// atomicMin on t0 returns the minimum before it, and whenever that is a
+// different tid, the larger of the two is offered to t1.  Every offer is a
+// tid of the cell other than the final t0, hence >= the second least tid;
+// and the second least tid is always offered (whether it comes before or
+// after the least one, or after a larger one), so t1 ends exact.
+DEV void cell_update(uint32_t *t0, uint32_t *t1, uint32_t *w0, uint32_t tid, bool wr) {
+    const uint32_t old = atomicMin(t0, tid);
+    if (old != NONE32 && old != tid) atomicMin(t1, old > tid ? old : tid);
+    if (wr) atomicMin(w0, tid);
+}
+
 // Exact decision of the filter's survivors by per-cell aggregation in an
 // LDS hash table at mem: open addressing on the cell's offset from lo (the
 // span is below 2^32), linear probing over 2^hb slots of (key, least tid,
@@ -1091,8 +1136,6 @@ static_assert(RED_OVF >= 4 * (TWG / 64) && RED_OVF < RED_NC && RED_NC < RED_CAND
 // overflow.  src(f) calls f(record) for each survivor this thread owns (the
 // same ones on every call).  Returns 1 (racy cell found), 0 (none) or -1
 // (overflow: the caller sorts instead).
-constexpr uint32_t HSLOTS_MAX = 4096;
-static_assert(HSLOTS_MAX * 16 <= TILE_LDS * 8, "hash table exceeds the group LDS");
 template <int NT, class Src>
 DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsigned long long lo, uint32_t *mem,
                  uint32_t max_slots, uint32_t *red, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
@@ -1122,8 +1165,7 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
             h = (h + 1) & (S - 1);
         }
         if (placed) {
-            atomicMin(&T0[h], tid);
-            if (r & 1ull) atomicMin(&W0[h], tid);
+            cell_update(T0 + h, T1 + h, W0 + h, tid, (r & 1ull) != 0);
         } else {
             ovf = true;
         }
@@ -1131,14 +1173,6 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
     if (ovf) red[RED_OVF] = 1;
     __syncthreads();
     if (red[RED_OVF]) return -1;
-    src([&](unsigned long long r) {
-        const uint32_t c = (uint32_t)((r >> ish) - lo);
-        const uint32_t tid = (uint32_t)(r >> 1) & tmask;
-        uint32_t h = (c * 0x9E3779B1u) >> (32 - hb);
-        while (K[h] != c) h = (h + 1) & (S - 1);   // placed in the pass before
-        if (tid != T0[h]) atomicMin(&T1[h], tid);
-    });
-    __syncthreads();
     // least racy cell, with its slot in the low bits (a cell has one slot)
     unsigned long long best = ~0ull, none = 0;
     for (uint32_t k = threadIdx.x; k < S; k += NT)
@@ -1164,23 +1198,26 @@ DEV uint32_t filter_bit(unsigned long long cell, unsigned long long lo, bool has
     return hashed ? (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64 - bits)) : (uint32_t)(cell - lo);
 }
 
-template <int E, int NT>
+// (a holds LW u64 words; larger sizes are never asked for: n is at most
+// the group's record count)
+template <int E, int NT, uint32_t LW>
 DEV void sort_e(unsigned long long *a, uint32_t n) {
-    if constexpr ((uint32_t)E * NT <= (uint32_t)TILE) block_sort_e<E, NT>(a, n);
+    if constexpr ((uint32_t)E * NT <= (uint32_t)TILE && (uint32_t)E * NT + (uint32_t)E * NT / 32 <= LW)
+        block_sort_e<E, NT>(a, n);
 }
 
 // Sorts a[0..n) (n a power of two, NT <= n <= TILE) with an NT-thread
 // workgroup and returns the first racy group of its cnt records.
-template <int NT>
+template <int NT, uint32_t LW>
 DEV bool sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t tb, uint32_t *red,
                    unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     switch (n / NT) {
-    case 1: sort_e<1, NT>(a, n); break;
-    case 2: sort_e<2, NT>(a, n); break;
-    case 4: sort_e<4, NT>(a, n); break;
-    case 8: sort_e<8, NT>(a, n); break;
-    case 16: sort_e<16, NT>(a, n); break;
-    default: sort_e<32, NT>(a, n); break;
+    case 1: sort_e<1, NT, LW>(a, n); break;
+    case 2: sort_e<2, NT, LW>(a, n); break;
+    case 4: sort_e<4, NT, LW>(a, n); break;
+    case 8: sort_e<8, NT, LW>(a, n); break;
+    case 16: sort_e<16, NT, LW>(a, n); break;
+    default: sort_e<32, NT, LW>(a, n); break;
     }
     return block_first_racy(a, cnt, tb, red, key, i1, i2);
 }
@@ -1189,9 +1226,11 @@ DEV bool sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t tb,
 // lanes past the end hold a copy of a real record) with the LDS array a
 // (TILE_LDS words) as scratch.  Returns whether a cell races, with the
 // least racy cell and its witness pair.
-template <int E, int NT>
+template <int E, int NT, uint32_t LW = TILE_LDS>
 DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, unsigned long long *a, uint32_t *red,
                 unsigned long long &key, uint32_t &i1, uint32_t &i2) {
+    using SC = Scratch<LW>;
+    static_assert((uint32_t)E * NT + (uint32_t)E * NT / 32 <= LW, "records exceed the scratch");
     const uint32_t ish = tb + 1;
     const uint32_t tmask = tb >= 32 ? 0xFFFFFFFFu : ((1u << tb) - 1u);
     uint32_t *w32 = reinterpret_cast<uint32_t *>(a);
@@ -1205,7 +1244,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
     block_minmax64(lo, hi, red);
     const unsigned long long span = hi - lo + 1;   // cells are below 2^63
 
-    if (span <= TBL_CELLS) {
+    if (span <= SC::tbl_cells) {
         const uint32_t sp = (uint32_t)span;
         uint32_t *t0 = w32, *w0 = w32 + sp, *t1 = w32 + 2 * sp;
         for (uint32_t k = threadIdx.x; k < 3 * sp; k += NT) w32[k] = NONE32;
@@ -1214,16 +1253,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         for (int j = 0; j < E; j++) {
             if ((uint32_t)j * NT + threadIdx.x < cnt) {
                 const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
-                atomicMin(&t0[b], tid);
-                if (u[j] & 1ull) atomicMin(&w0[b], tid);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
-                if (tid != t0[b]) atomicMin(&t1[b], tid);
+                cell_update(t0 + b, t1 + b, w0 + b, tid, (u[j] & 1ull) != 0);
             }
         }
         __syncthreads();
@@ -1252,10 +1282,10 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
     // read)
     uint32_t keepm = 0, nc;
     {
-        const bool hashed = span > (1ull << FILTER_BITS);
+        const bool hashed = span > (1ull << SC::fbits);
         // bitmap words, a multiple of four: cleared 16 bytes at a time
-        const uint32_t nw = hashed ? FILTER_WORDS : (((uint32_t)((span + 31) >> 5) + 3u) & ~3u);
-        uint32_t *seen = w32, *rep = w32 + FILTER_WORDS;
+        const uint32_t nw = hashed ? SC::fwords : (((uint32_t)((span + 31) >> 5) + 3u) & ~3u);
+        uint32_t *seen = w32, *rep = w32 + SC::fwords;
         uint4 *seen4 = reinterpret_cast<uint4 *>(seen), *rep4 = reinterpret_cast<uint4 *>(rep);
         for (uint32_t q = threadIdx.x; q < nw / 4; q += NT) {
             seen4[q] = make_uint4(0u, 0u, 0u, 0u);
@@ -1270,7 +1300,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS), bit = 1u << (b & 31);
+                const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, SC::fbits), bit = 1u << (b & 31);
                 if (atomicOr(&seen[b >> 5], bit) & bit) {
                     atomicOr(&rep[b >> 5], bit);
                     again = true;
@@ -1282,7 +1312,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         if (red[RED_CAND] == 0) return false;   // every cell touched once
 #pragma unroll
         for (int j = 0; j < E; j++) {
-            const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, FILTER_BITS);
+            const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, SC::fbits);
             const bool keep = (uint32_t)j * NT + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
             const uint64_t m = ballot(keep);
             if (m) {
@@ -1291,13 +1321,13 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
                 if (lane_id() == 0) base = atomicAdd(&red[RED_NC], (uint32_t)__builtin_popcountll(m));
                 base = __shfl(base, 0);
                 const uint32_t pos = base + mbcnt(m);
-                if (keep && pos < SURV_CAP) a[ph(pos)] = u[j];
+                if (keep && pos < SC::surv_cap) a[ph(pos)] = u[j];
             }
         }
         __syncthreads();   // the bitmaps are read for the last time
         nc = red[RED_NC];
     }
-    const bool compact = nc <= SURV_CAP;
+    const bool compact = nc <= SC::surv_cap;
     if (span <= 0xFFFFFFFFull) {
         int r;
         if (compact) {
@@ -1305,15 +1335,15 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
             auto src = [&](auto f) {
                 for (uint32_t i = threadIdx.x; i < nc; i += NT) f(a[ph(i)]);
             };
-            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32 + SURV_WORDS, (2 * TILE_LDS - SURV_WORDS) / 4, red, key,
-                             i1, i2);
+            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32 + SC::surv_words, (SC::words - SC::surv_words) / 4, red,
+                             key, i1, i2);
         } else {
             auto src = [&](auto f) {
 #pragma unroll
                 for (int j = 0; j < E; j++)
                     if ((keepm >> j) & 1u) f(u[j]);
             };
-            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32, HSLOTS_MAX, red, key, i1, i2);
+            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32, SC::hslots, red, key, i1, i2);
         }
         if (r >= 0) return r == 1;
         __syncthreads();   // every thread has seen the overflow
@@ -1338,7 +1368,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
     while (np < nc) np <<= 1;
     for (uint32_t k = nc + threadIdx.x; k < np; k += NT) a[ph(k)] = ~0ull;
     __syncthreads();
-    return sort_scan<NT>(a, np, nc, tb, red, key, i1, i2);
+    return sort_scan<NT, LW>(a, np, nc, tb, red, key, i1, i2);
 }
 
 // =============================================================== fused path
@@ -1352,6 +1382,7 @@ struct FusedSink {
     unsigned long long pre;     // phase-in-group prefix of the key
     uint32_t ish;               // index shift (tid bits + 1)
     uint32_t tid;
+    uint32_t cap;               // records the LDS array holds
     DEV void acc(bool act, uint32_t idx, uint32_t mode) {
         const uint64_t m = ballot(act);
         if (m == 0) return;
@@ -1359,7 +1390,7 @@ struct FusedSink {
         if (lane_id() == 0) off = atomicAdd(lds_n, (uint32_t)__builtin_popcountll(m));
         off = __shfl(off, 0);
         const uint32_t pos = off + mbcnt(m);
-        if (act && pos < (uint32_t)TILE)
+        if (act && pos < cap)
             lds[ph(pos)] = pre | ((unsigned long long)idx << ish) | ((unsigned long long)tid << 1) | mode;
     }
 };
@@ -1374,7 +1405,7 @@ constexpr uint32_t STAGE_WORDS = 2048;
 // words each: the fixed-form words and op count of the compiled access,
 // then the offset of its op list in the code blob), and the nests with
 // iterations in the unit are listed (act_*) when all of them are staged.
-constexpr uint32_t HSTRIDE = 12;
+constexpr uint32_t HSTRIDE = 16;
 static_assert(CAL_HDR + 1 <= HSTRIDE, "decoded access header");
 struct FusedStage {
     uint32_t base[FN_CACHE];            // first word of the nest's block in w, or NONE32 (not staged)
@@ -1393,18 +1424,13 @@ DEV uint32_t cal_index_lane(const uint32_t *hp, const uint32_t *__restrict__ cod
                             uint32_t ustride) {
     if (hp[1] == 1u) {
         const uint32_t c0 = hp[2], m0k = hp[3], m0 = hp[4], a = hp[5], us = hp[6], pk = hp[7], pa = hp[8];
-        uint32_t v = tid + c0;
-        if (m0k == CAL_K_AND) v &= m0;
-        else if (m0k == CAL_K_MOD) v = m0 ? v % m0 : v;
-        v *= a;
+        uint32_t v = fixed_op(tid + c0, m0k, m0, hp[9], hp[10]) * a;
         if (us != NONE32) v += U[us * ustride];
-        if (pk == CAL_K_AND) v &= pa;
-        else if (pk == CAL_K_MOD) v = pa ? v % pa : v;
-        return v;
+        return fixed_op(v, pk, pa, hp[11], hp[12]);
     }
-    const uint32_t *op = code + hp[10];
+    const uint32_t *op = code + hp[CAL_HDR];
     uint32_t v = tid;
-    for (uint32_t o = 0; o < hp[9]; o++) {
+    for (uint32_t o = 0; o < hp[CAL_HDR - 1]; o++) {
         const uint32_t opw = op[2 * o], arg = op[2 * o + 1];
         const uint32_t x = (opw & C_UNI) ? U[arg * ustride] : arg;
         switch (opw & 0xFFu) {
@@ -1424,14 +1450,16 @@ DEV uint32_t cal_index_lane(const uint32_t *hp, const uint32_t *__restrict__ cod
     return v;
 }
 
-template <typename T, bool WIDE>
+template <typename T, bool WIDE, uint32_t FT = TILE>
 DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
                     const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,
                     const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
                     unsigned long long *__restrict__ phase_counts, unsigned long long *__restrict__ nrec,
                     uint32_t *__restrict__ ovf_flags, Cand *__restrict__ cands, Best *__restrict__ best,
                     uint32_t tile) {
-    __shared__ __align__(16) unsigned long long lds_rec[TILE_LDS];
+    constexpr uint32_t FT_LDS = FT + FT / 32;
+    constexpr uint32_t PACK = FUSED_PACK < FT ? FUSED_PACK : FT;
+    __shared__ __align__(16) unsigned long long lds_rec[FT_LDS];
     __shared__ uint32_t lds_n;
     __shared__ uint32_t lds_res[RED_WORDS];
     __shared__ uint32_t lds_unit;
@@ -1614,7 +1642,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                     c = pd.phase_bound;
                 }
                 // a packed group's phases must fit the key bits above the index
-                if (any && (!pack || est + c > (uint32_t)FUSED_PACK || ((k - gk0) >> (64 - psh)) != 0)) break;
+                if (any && (!pack || est + c > PACK || ((k - gk0) >> (64 - psh)) != 0)) break;
                 const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
                 if (fast) {
                     for (uint32_t a = 0; a < nact; a++) {
@@ -1641,7 +1669,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                                     const uint32_t *hp = hp0 + j * HSTRIDE;
                                     const uint32_t v = cal_index_lane(hp, code, tid, U, cs);
                                     const uint32_t pos = off + e;
-                                    if (pos < (uint32_t)TILE)
+                                    if (pos < FT)
                                         lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
                                                            ((unsigned long long)tid << 1) | hp[0];
                                 }
@@ -1687,7 +1715,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                                         const uint32_t mode = rfl(ap[0]);
                                         const uint32_t v = cal_index(ap, tid, U, cs);
                                         const uint32_t pos = p0 + j * na;
-                                        if (act && pos < (uint32_t)TILE)
+                                        if (act && pos < FT)
                                             lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
                                                                ((unsigned long long)tid << 1) | mode;
                                         ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
@@ -1714,7 +1742,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
                         const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
                         for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
                             const uint32_t tid = t0 + threadIdx.x;
-                            FusedSink sink{lds_rec, &lds_n, pre, ish, tid};
+                            FusedSink sink{lds_rec, &lds_n, pre, ish, tid, FT};
                             run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
                         }
                         odo.next(nd, vars);
@@ -1736,12 +1764,12 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             __syncthreads();
             uint32_t cnt = fast ? off : lds_n;
             total += cnt;
-            if (cnt > (uint32_t)TILE) {
+            if (cnt > FT) {
                 // more events than the count or the plan bounded: the records
                 // past the tile were dropped, so the protocol gets an error
                 // status instead of a verdict
                 if (threadIdx.x == 0) atomicOr(&ovf_flags[u.proto], OVF_LIMIT);
-                cnt = TILE;
+                cnt = FT;
             }
             if (cnt == 0) {
                 __syncthreads();
@@ -1749,7 +1777,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             }
             // the records move to registers (lanes past the end copy a real
             // one) and the whole LDS array becomes the decision's scratch
-            constexpr int FE = TILE / WG;
+            constexpr int FE = FT / WG;
             unsigned long long v[FE];
 #pragma unroll
             for (int jj = 0; jj < FE; jj++) {
@@ -1760,7 +1788,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             __syncthreads();
             unsigned long long key = 0;
             uint32_t r1 = 0, r2 = 0;
-            const bool f = decide<FE, WG>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
+            const bool f = decide<FE, WG, FT_LDS>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
             if (f && !have) {
                 have = true;
                 const uint64_t kk = gk0 + (pack ? (key >> pd.ib) : 0ull);
