@@ -1450,6 +1450,75 @@ DEV uint32_t cal_index_lane(const uint32_t *hp, const uint32_t *__restrict__ cod
     return v;
 }
 
+
+// ------------------------------------------- fused path: records in registers
+// When every nest with iterations in a unit is staged, the unit's records
+// are known by arithmetic: iteration i of listed nest a holds
+// nacc_a * min(limit_i, n) records (access-major: record e is access
+// e / L of tid e mod L).  The thread limits of the staged iterations are
+// replaced by the prefix sums of these counts, and each thread then
+// generates the records of a group at its own positions straight into
+// registers (a cursor over the prefix sums), with no LDS record writes and
+// no per-phase loop.
+struct FastLds {
+    uint32_t ptot[FN_CACHE];          // records of each listed nest's staged iterations
+    uint32_t nbase[FN_CACHE + 1];     // prefix of the flat iteration list at each nest's first
+    uint32_t mag[FN_CACHE], sh[FN_CACHE];   // division by each nest's access count
+    uint32_t gs[64], ge[64], gc[64];  // groups of a window: phase offsets [gs, ge), records
+    uint32_t ng;
+    uint32_t G[FN_CACHE], ilo[FN_CACHE], plo[FN_CACHE];   // per group and nest: first record,
+                                                           // first iteration, prefix there
+};
+
+// Division magic of d >= 1 for 32-bit dividends (the same construction as
+// the planner's: Granlund and Montgomery, unsigned case).
+DEV void div_magic_dev(uint32_t d, uint32_t &mag, uint32_t &sh) {
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) l++;
+    mag = (uint32_t)(((((1ull << l) - d) << 32) / d) + 1);
+    sh = (l < 1 ? l : 1u) | ((l > 0 ? l - 1 : 0u) << 8);
+}
+DEV uint32_t div_by_magic(uint32_t x, uint32_t mag, uint32_t sh) {
+    const uint32_t t = __umulhi(mag, x);
+    return (t + ((x - t) >> (sh & 0xFFu))) >> (sh >> 8);
+}
+
+// First position in the non-decreasing ph[0..n) holding a value >= key.
+DEV uint32_t lower_bound_u32(const uint32_t *ph, uint32_t n, uint32_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (ph[m] < key) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+constexpr uint32_t FAST_CAP = 1u << 31;   // unit records the prefix sums may reach
+DEV uint32_t sat_add(uint32_t a, uint32_t b) { return a + b < FAST_CAP && a + b >= a ? a + b : FAST_CAP; }
+
+// Block-wide exclusive prefix of v (saturating at FAST_CAP); *total gets the
+// saturated sum.  red: at least WG / 64 words.
+DEV uint32_t block_excl_sat(uint32_t v, uint32_t *red, uint32_t &total) {
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, (unsigned)o);
+        if ((int)lane_id() >= o) x = sat_add(x, y);
+    }
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane_id() == 63) red[w] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (uint32_t q = 0; q < WG / 64; q++) {
+        const uint32_t r = red[q];
+        if (q < w) base = sat_add(base, r);
+        tot = sat_add(tot, r);
+    }
+    total = tot;
+    __syncthreads();
+    return sat_add(base, x) - v;   // exact whenever the total is below FAST_CAP
+}
+
 template <typename T, bool WIDE, uint32_t FT = TILE>
 DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
                     const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,
@@ -1468,11 +1537,8 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
     // first FN_CACHE nests (each wave reads only its own row: no barrier)
     __shared__ unsigned long long lds_nf[WG / 64][FN_CACHE];
     __shared__ FusedStage lds_st;
-    // per wave, in the all-staged mode: each listed nest's next staged
-    // iteration, and the first one past the current phase
-    __shared__ uint32_t lds_cur[WG / 64][FN_CACHE], lds_nx[WG / 64][FN_CACHE];
+    __shared__ FastLds lds_fx;
     unsigned long long *nf = lds_nf[threadIdx.x >> 6];
-    uint32_t *cur = lds_cur[threadIdx.x >> 6], *nx = lds_nx[threadIdx.x >> 6];
     // persistent: workgroups pull units (largest first) from a device queue
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1589,180 +1655,342 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
             }
             __syncthreads();
         }
-        // When every nest with iterations in the unit is staged, each active
-        // lane writes exactly nacc records per iteration: record positions
-        // follow from the (uniform) running count and per-phase counts from
-        // arithmetic, with no atomics and no barrier per phase.
-        bool fast = false;
-        uint32_t nact = 0;
+        // Records of a unit are produced group by group into LDS, by one of
+        // two producers, then decided by the same code.  The arithmetic
+        // producer runs when every nest with iterations in the unit is staged
+        // and the unit's records stay below 2^31; the other one evaluates
+        // the nests phase by phase.
+        bool done = false;   // the arithmetic producer is used
         if constexpr (!WIDE) {
-            fast = lds_st.all != 0;
-            nact = lds_st.nact;
-            for (uint32_t a = lane_id(); a < nact; a += 64) cur[a] = 0;
-        }
-        uint64_t k = u.k0;
-        while (k < u.k1) {
-            // one group of consecutive phases whose events fit one tile
-            uint64_t gk0 = k;
-            if (threadIdx.x == 0) lds_n = 0;
-            __syncthreads();
-            uint32_t est = 0, before = 0, off = 0;
-            bool any = false;
-            while (k < u.k1) {
-                uint32_t c;
-                if (fast) {
-                    // exact records of phase k: the staged iterations at k
-                    const uint32_t kr = (uint32_t)(k - u.k0);
-                    c = 0;
-                    for (uint32_t a = 0; a < nact; a++) {
-                        const uint32_t sb = rfl(lds_st.act_sb[a]), cs = rfl(lds_st.act_cs[a]);
-                        const uint32_t na = rfl(lds_st.act_nacc[a]);
-                        uint32_t i = rfl(cur[a]);
-                        for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
-                            const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
-                            c += na * (lim < pd.n ? lim : pd.n);
+            if (lds_st.all != 0) {
+                const uint32_t nact = lds_st.nact;
+                // per-iteration record counts, their prefix sums over the flat
+                // list of staged iterations (nest after nest), four a thread
+                uint32_t nflat = 0;
+                for (uint32_t a = 0; a < nact; a++) nflat += lds_st.act_cs[a];
+                uint32_t rr[4], loc = 0, fa[4], fi[4];
+                {
+                    uint32_t a = 0, F = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t f = 4 * threadIdx.x + (uint32_t)q;
+                        rr[q] = 0;
+                        fa[q] = NONE32;
+                        fi[q] = 0;
+                        if (f < nflat) {
+                            while (f >= F + lds_st.act_cs[a]) F += lds_st.act_cs[a++];
+                            const uint32_t cs = lds_st.act_cs[a], i = f - F;
+                            const uint32_t lim = lds_st.w[lds_st.act_sb[a] + cs + i];
+                            const uint64_t r = (uint64_t)lds_st.act_nacc[a] * (lim < pd.n ? lim : pd.n);
+                            rr[q] = r < FAST_CAP ? (uint32_t)r : FAST_CAP;
+                            fa[q] = a;
+                            fi[q] = i;
                         }
-                        nx[a] = i;
+                        loc = sat_add(loc, rr[q]);
                     }
-                    if (c == 0 || c > tile) {   // no records, or in HBM
-                        for (uint32_t a = lane_id(); a < nact; a += 64) cur[a] = nx[a];
-                        k++;
-                        if (!any) gk0 = k;
-                        continue;
-                    }
-                } else if (!stat) {
-                    const unsigned long long ck = phase_counts[k];
-                    if (ck == 0 || ck > (unsigned long long)tile) {   // empty or in HBM
-                        k++;
-                        if (!any) gk0 = k;
-                        continue;
-                    }
-                    c = (uint32_t)ck;
-                } else {
-                    c = pd.phase_bound;
                 }
-                // a packed group's phases must fit the key bits above the index
-                if (any && (!pack || est + c > PACK || ((k - gk0) >> (64 - psh)) != 0)) break;
-                const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
-                if (fast) {
-                    for (uint32_t a = 0; a < nact; a++) {
-                        const uint32_t sb = rfl(lds_st.act_sb[a]), cs = rfl(lds_st.act_cs[a]);
-                        const uint32_t nacc = rfl(lds_st.act_nacc[a]);
-                        const uint32_t *hp0 = lds_st.w + rfl(lds_st.act_hofs[a]);
-                        const uint32_t i1 = rfl(nx[a]);
-                        for (uint32_t i = rfl(cur[a]); i < i1; i++) {
-                            const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
-                            const uint32_t *U = lds_st.w + sb + 2 * cs + i;
-                            // active tids are [0, L); the iteration's L * nacc
-                            // records are spread over the lanes, access-major:
-                            // record e is access e / L of tid e % L (the
-                            // division by a multiply-high, exact since e and L
-                            // are at most one tile)
-                            const uint32_t L = lim < pd.n ? lim : pd.n;
-                            const uint32_t R = L * nacc;
-                            const uint32_t M = L > 1 ? 0xFFFFFFFFu / L + 1u : 0u;
-                            for (uint32_t e0 = 0; e0 < R; e0 += WG) {
-                                const uint32_t e = e0 + threadIdx.x;
-                                if (e < R) {
-                                    const uint32_t j = L > 1 ? __umulhi(e, M) : e;
-                                    const uint32_t tid = e - j * L;
-                                    const uint32_t *hp = hp0 + j * HSTRIDE;
+                uint32_t tot = 0;
+                const uint32_t excl = block_excl_sat(loc, lds_res, tot);
+                if (tot < FAST_CAP) {
+                    done = true;
+                    uint32_t pf[4];
+                    {
+                        uint32_t run = excl;
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            pf[q] = run;
+                            run += rr[q];
+                            if (fa[q] != NONE32 && fi[q] == 0) lds_fx.nbase[fa[q]] = pf[q];
+                        }
+                    }
+                    if (threadIdx.x == 0) lds_fx.nbase[nact] = tot;
+                    __syncthreads();
+                    // the thread limits become the prefix sums within each nest
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (fa[q] != NONE32)
+                            lds_st.w[lds_st.act_sb[fa[q]] + lds_st.act_cs[fa[q]] + fi[q]] = pf[q] - lds_fx.nbase[fa[q]];
+                    if (threadIdx.x < nact) {
+                        const uint32_t a = threadIdx.x;
+                        lds_fx.ptot[a] = lds_fx.nbase[a + 1] - lds_fx.nbase[a];
+                        div_magic_dev(lds_st.act_nacc[a], lds_fx.mag[a], lds_fx.sh[a]);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        // prefix of listed nest a at staged iteration i (i <= cs)
+        auto pref = [&](uint32_t a, uint32_t i) -> uint32_t {
+            const uint32_t cs = lds_st.act_cs[a];
+            return i < cs ? lds_st.w[lds_st.act_sb[a] + cs + i] : lds_fx.ptot[a];
+        };
+        uint64_t k = u.k0;                 // next phase (evaluating producer)
+        uint64_t kw = u.k0, kwc = u.k0;    // next window / current window (arithmetic producer)
+        uint32_t g = 0, ngr = 0;           // next group of the current window, groups in it
+        for (;;) {
+            uint64_t gk0;
+            uint32_t cnt;
+            if (done) {
+                const uint32_t nact = lds_st.nact;
+                if (g == ngr) {
+                    if (kw >= u.k1) break;
+                    // the next window of up to 64 phases: records of each phase
+                    // (a lane per phase), then phases packed into groups
+                    const uint32_t nw = (uint32_t)(u.k1 - kw < 64 ? u.k1 - kw : 64);
+                    const uint32_t krw = (uint32_t)(kw - u.k0);
+                    if (threadIdx.x < 64) {
+                        const uint32_t l = threadIdx.x;
+                        uint32_t c = 0;
+                        if (l < nw) {
+                            for (uint32_t a = 0; a < nact; a++) {
+                                const uint32_t *phs = lds_st.w + lds_st.act_sb[a];
+                                const uint32_t cs = lds_st.act_cs[a];
+                                const uint32_t lo = lower_bound_u32(phs, cs, krw + l);
+                                const uint32_t hi = lower_bound_u32(phs, cs, krw + l + 1);
+                                c += pref(a, hi) - pref(a, lo);
+                            }
+                            if (stat && c != 0) phase_counts[kw + l] = c;
+                        }
+                        // the same scalar loop on every lane: empty phases are
+                        // passed over, a phase above the tile (in HBM) ends a group
+                        uint32_t ng = 0, est = 0, gs = NONE32;
+                        for (uint32_t q = 0; q < nw; q++) {
+                            const uint32_t cq = readlane(c, q);
+                            if (cq == 0) continue;
+                            const bool big = cq > tile;
+                            if (gs != NONE32 &&
+                                (big || !pack || est + cq > PACK || ((uint64_t)(q - gs) >> (64 - psh)) != 0)) {
+                                if (l == 0) {
+                                    lds_fx.gs[ng] = gs;
+                                    lds_fx.ge[ng] = q;
+                                    lds_fx.gc[ng] = est;
+                                }
+                                ng++;
+                                gs = NONE32;
+                            }
+                            if (big) continue;
+                            if (gs == NONE32) {
+                                gs = q;
+                                est = 0;
+                            }
+                            est += cq;
+                        }
+                        if (gs != NONE32) {
+                            if (l == 0) {
+                                lds_fx.gs[ng] = gs;
+                                lds_fx.ge[ng] = nw;
+                                lds_fx.gc[ng] = est;
+                            }
+                            ng++;
+                        }
+                        if (l == 0) lds_fx.ng = ng;
+                    }
+                    __syncthreads();
+                    ngr = lds_fx.ng;
+                    g = 0;
+                    kwc = kw;
+                    kw += 64;
+                    __syncthreads();   // lds_fx.ng is read before the next window writes it
+                    continue;
+                }
+                const uint32_t gs = lds_fx.gs[g], ge = lds_fx.ge[g];
+                cnt = lds_fx.gc[g];
+                g++;
+                gk0 = kwc + gs;
+                const uint32_t krw = (uint32_t)(kwc - u.k0);
+                if (threadIdx.x < 64) {
+                    // each nest's first record, first iteration and prefix there
+                    const uint32_t a = threadIdx.x;
+                    uint32_t q = 0, ilo = 0, plo = 0;
+                    if (a < nact) {
+                        const uint32_t *phs = lds_st.w + lds_st.act_sb[a];
+                        const uint32_t cs = lds_st.act_cs[a];
+                        ilo = lower_bound_u32(phs, cs, krw + gs);
+                        const uint32_t ihi = lower_bound_u32(phs, cs, krw + ge);
+                        plo = pref(a, ilo);
+                        q = pref(a, ihi) - plo;
+                    }
+                    uint32_t inc = q;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t y = __shfl_up(inc, (unsigned)o);
+                        if ((int)lane_id() >= o) inc += y;
+                    }
+                    if (a < nact) {
+                        lds_fx.G[a] = inc - q;
+                        lds_fx.ilo[a] = ilo;
+                        lds_fx.plo[a] = plo;
+                    }
+                }
+                __syncthreads();
+                // each thread writes a contiguous block of the group's records;
+                // it locates its first record (nest by the group bases,
+                // iteration by a binary search over the prefix sums), then
+                // walks tid, access and iteration forward (access-major:
+                // record e of an iteration is access e / L of tid e mod L)
+                {
+                    const uint32_t per = (cnt + WG - 1) / WG;
+                    uint32_t p = threadIdx.x * per;
+                    const uint32_t pend = p + per < cnt ? p + per : cnt;
+                    while (p < pend) {
+                        uint32_t a = 0;
+                        for (uint32_t b = 1; b < nact; b++)
+                            if (lds_fx.G[b] <= p) a = b;
+                        const uint32_t sb = lds_st.act_sb[a], cs = lds_st.act_cs[a], na = lds_st.act_nacc[a];
+                        const uint32_t ptot = lds_fx.ptot[a];
+                        const uint32_t *P = lds_st.w + sb + cs;        // prefix sums of nest a
+                        const uint32_t qq = p - lds_fx.G[a] + lds_fx.plo[a];
+                        // the largest i in [ilo, cs) with P[i] <= qq (P[cs] = ptot > qq)
+                        uint32_t lo = lds_fx.ilo[a], hi = cs - 1;
+                        while (lo < hi) {
+                            const uint32_t m = (lo + hi + 1) >> 1;
+                            if (P[m] <= qq) lo = m;
+                            else hi = m - 1;
+                        }
+                        const uint32_t i = lo;
+                        const uint32_t p0 = P[i], pn = i + 1 < cs ? P[i + 1] : ptot;
+                        const uint32_t L = div_by_magic(pn - p0, lds_fx.mag[a], lds_fx.sh[a]);
+                        uint32_t tid = qq - p0, j = 0;
+                        while (tid >= L && j + 1 < na) {   // j < na: the iteration holds na * L records
+                            tid -= L;
+                            j++;
+                        }
+                        if (tid >= L) break;   // cannot happen (qq < pn = p0 + na * L); ends the block
+                        const uint32_t *U = lds_st.w + sb + 2 * cs + i;
+                        const unsigned long long pre =
+                            pack ? ((unsigned long long)(lds_st.w[sb + i] + u.k0 - gk0) << psh) : 0ull;
+                        // the rest of this iteration, access by access
+                        for (; j < na && p < pend; j++) {
+                            const uint32_t *hp = lds_st.w + lds_st.act_hofs[a] + j * HSTRIDE;
+                            const uint32_t mode = hp[0];
+                            const uint32_t t1 = tid + (pend - p < L - tid ? pend - p : L - tid);
+                            if (hp[1] == 1u) {
+                                const uint32_t c0 = hp[2], m0k = hp[3], m0 = hp[4], am = hp[5], us = hp[6];
+                                const uint32_t pk = hp[7], pa = hp[8], m0mag = hp[9], m0sh = hp[10];
+                                const uint32_t pamag = hp[11], pash = hp[12];
+                                const uint32_t uv = us != NONE32 ? U[us * cs] : 0u;
+                                for (; tid < t1; tid++, p++) {
+                                    const uint32_t v = fixed_op(fixed_op(tid + c0, m0k, m0, m0mag, m0sh) * am + uv, pk, pa,
+                                                                pamag, pash);
+                                    lds_rec[ph(p)] = pre | ((unsigned long long)v << ish) |
+                                                     ((unsigned long long)tid << 1) | mode;
+                                }
+                            } else {
+                                for (; tid < t1; tid++, p++) {
                                     const uint32_t v = cal_index_lane(hp, code, tid, U, cs);
-                                    const uint32_t pos = off + e;
-                                    if (pos < FT)
-                                        lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
-                                                           ((unsigned long long)tid << 1) | hp[0];
+                                    lds_rec[ph(p)] = pre | ((unsigned long long)v << ish) |
+                                                     ((unsigned long long)tid << 1) | mode;
                                 }
                             }
-                            off += R;
+                            tid = 0;
                         }
-                        cur[a] = i1;
                     }
-                    if (stat && threadIdx.x == 0) phase_counts[k] = c;
+                }
+                __syncthreads();
+            } else {
+                // one group of consecutive phases whose events fit one tile
+                gk0 = k;
+                if (threadIdx.x == 0) lds_n = 0;
+                __syncthreads();
+                if (threadIdx.x == 0) lds_n = 0;
+                __syncthreads();
+                uint32_t est = 0, before = 0;
+                bool any = false;
+                while (k < u.k1) {
+                    uint32_t c;
+                    if (!stat) {
+                        const unsigned long long ck = phase_counts[k];
+                        if (ck == 0 || ck > (unsigned long long)tile) {   // empty or in HBM
+                            k++;
+                            if (!any) gk0 = k;
+                            continue;
+                        }
+                        c = (uint32_t)ck;
+                    } else {
+                        c = pd.phase_bound;
+                    }
+                    // a packed group's phases must fit the key bits above the index
+                    if (any && (!pack || est + c > PACK || ((k - gk0) >> (64 - psh)) != 0)) break;
+                    const unsigned long long pre = pack ? ((unsigned long long)(k - gk0) << psh) : 0ull;
+                    for (uint32_t ni = 0; ni < pd.nnests; ni++) {
+                        const NestDesc &nd = nests[pd.nest0 + ni];
+                        if (k < nd.phase_base || k > nd.phase_last) continue;
+                        if constexpr (!WIDE) {
+                            const uint32_t sb = ni < ncache ? lds_st.base[ni] : NONE32;
+                            if (sb != NONE32) {
+                                const uint32_t cs = lds_st.cnt[ni];
+                                const uint32_t kr = (uint32_t)(k - u.k0);
+                                uint32_t i = (uint32_t)(nf[ni] - lds_st.f0[ni]);
+                                while (i < cs && rfl(lds_st.w[sb + i]) < kr) i++;   // phases skipped since
+                                const uint32_t *cal = code + nd.cal_off;
+                                const uint32_t nacc = rfl(cal[0]);
+                                const uint32_t *acc0 = cal + rfl(lds_st.acc[ni]);
+                                for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
+                                    const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
+                                    const uint32_t *U = lds_st.w + sb + 2 * cs + i;
+                                    for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
+                                        const uint32_t tid = t0 + threadIdx.x;
+                                        const bool act = tid < pd.n && tid < lim;
+                                        // one reservation per wave for all accesses (no branches)
+                                        const uint64_t m = ballot(act);
+                                        if (m == 0) continue;
+                                        const uint32_t na = (uint32_t)__builtin_popcountll(m);
+                                        uint32_t r0 = 0;
+                                        if (lane_id() == 0) r0 = atomicAdd(&lds_n, na * nacc);
+                                        const uint32_t p0 = readlane(r0, 0) + mbcnt(m);
+                                        const uint32_t *ap = acc0;
+                                        for (uint32_t j = 0; j < nacc; j++) {
+                                            const uint32_t mode = rfl(ap[0]);
+                                            const uint32_t v = cal_index(ap, tid, U, cs);
+                                            const uint32_t pos = p0 + j * na;
+                                            if (act && pos < FT)
+                                                lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
+                                                                   ((unsigned long long)tid << 1) | mode;
+                                            ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
+                                        }
+                                    }
+                                }
+                                nf[ni] = lds_st.f0[ni] + i;
+                                continue;
+                            }
+                        }
+                        // the cached iteration is the first of phase k unless
+                        // phases were skipped since (then search again)
+                        uint64_t fa = ni < ncache ? nf[ni] : first_iter_at(nd, k);
+                        if (fa < nd.iters && phase_of(nd, fa) < k) fa = first_iter_at(nd, k);
+                        if (fa >= nd.iters) continue;
+                        T vars[MAXSLOTS];
+                        for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
+                        load_fixed<T>(nd, fixed, vars);
+                        Odo<T> odo;
+                        odo.start(nd, fa, vars);
+                        const uint32_t *leaf = code + nd.code_off;
+                        uint64_t f = fa;
+                        for (; f < nd.iters && odo.phase == k; f++) {
+                            const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
+                            for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
+                                const uint32_t tid = t0 + threadIdx.x;
+                                FusedSink sink{lds_rec, &lds_n, pre, ish, tid, FT};
+                                run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
+                            }
+                            odo.next(nd, vars);
+                        }
+                        if (ni < ncache) nf[ni] = f;
+                    }
+                    if (stat) {
+                        __syncthreads();
+                        const uint32_t now = lds_n;
+                        if (threadIdx.x == 0) phase_counts[k] = now - before;
+                        before = now;
+                        __syncthreads();
+                    }
                     est += c;
                     any = true;
                     k++;
-                    continue;
                 }
-                for (uint32_t ni = 0; ni < pd.nnests; ni++) {
-                    const NestDesc &nd = nests[pd.nest0 + ni];
-                    if (k < nd.phase_base || k > nd.phase_last) continue;
-                    if constexpr (!WIDE) {
-                        const uint32_t sb = ni < ncache ? lds_st.base[ni] : NONE32;
-                        if (sb != NONE32) {
-                            const uint32_t cs = lds_st.cnt[ni];
-                            const uint32_t kr = (uint32_t)(k - u.k0);
-                            uint32_t i = (uint32_t)(nf[ni] - lds_st.f0[ni]);
-                            while (i < cs && rfl(lds_st.w[sb + i]) < kr) i++;   // phases skipped since
-                            const uint32_t *cal = code + nd.cal_off;
-                            const uint32_t nacc = rfl(cal[0]);
-                            const uint32_t *acc0 = cal + rfl(lds_st.acc[ni]);
-                            for (; i < cs && rfl(lds_st.w[sb + i]) == kr; i++) {
-                                const uint32_t lim = rfl(lds_st.w[sb + cs + i]);
-                                const uint32_t *U = lds_st.w + sb + 2 * cs + i;
-                                for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
-                                    const uint32_t tid = t0 + threadIdx.x;
-                                    const bool act = tid < pd.n && tid < lim;
-                                    // one reservation per wave for all accesses (no branches)
-                                    const uint64_t m = ballot(act);
-                                    if (m == 0) continue;
-                                    const uint32_t na = (uint32_t)__builtin_popcountll(m);
-                                    uint32_t r0 = 0;
-                                    if (lane_id() == 0) r0 = atomicAdd(&lds_n, na * nacc);
-                                    const uint32_t p0 = readlane(r0, 0) + mbcnt(m);
-                                    const uint32_t *ap = acc0;
-                                    for (uint32_t j = 0; j < nacc; j++) {
-                                        const uint32_t mode = rfl(ap[0]);
-                                        const uint32_t v = cal_index(ap, tid, U, cs);
-                                        const uint32_t pos = p0 + j * na;
-                                        if (act && pos < FT)
-                                            lds_rec[ph(pos)] = pre | ((unsigned long long)v << ish) |
-                                                               ((unsigned long long)tid << 1) | mode;
-                                        ap += CAL_HDR + 2 * rfl(ap[CAL_HDR - 1]);
-                                    }
-                                }
-                            }
-                            nf[ni] = lds_st.f0[ni] + i;
-                            continue;
-                        }
-                    }
-                    // the cached iteration is the first of phase k unless
-                    // phases were skipped since (then search again)
-                    uint64_t fa = ni < ncache ? nf[ni] : first_iter_at(nd, k);
-                    if (fa < nd.iters && phase_of(nd, fa) < k) fa = first_iter_at(nd, k);
-                    if (fa >= nd.iters) continue;
-                    T vars[MAXSLOTS];
-                    for (int s = 0; s < MAXSLOTS; s++) vars[s] = 0;
-                    load_fixed<T>(nd, fixed, vars);
-                    Odo<T> odo;
-                    odo.start(nd, fa, vars);
-                    const uint32_t *leaf = code + nd.code_off;
-                    uint64_t f = fa;
-                    for (; f < nd.iters && odo.phase == k; f++) {
-                        const uint32_t lim = tid_limit<T>(nd, code, vars, pd.n);
-                        for (uint32_t t0 = 0; t0 < lim; t0 += WG) {
-                            const uint32_t tid = t0 + threadIdx.x;
-                            FusedSink sink{lds_rec, &lds_n, pre, ish, tid, FT};
-                            run_leaf<T, WIDE>(leaf, vars, (T)tid, tid < pd.n, ovf, sink);
-                        }
-                        odo.next(nd, vars);
-                    }
-                    if (ni < ncache) nf[ni] = f;
-                }
-                if (stat) {
-                    __syncthreads();
-                    const uint32_t now = lds_n;
-                    if (threadIdx.x == 0) phase_counts[k] = now - before;
-                    before = now;
-                    __syncthreads();
-                }
-                est += c;
-                any = true;
-                k++;
+                if (!any) break;
+                __syncthreads();
+                cnt = lds_n;
             }
-            if (!any) break;
-            __syncthreads();
-            uint32_t cnt = fast ? off : lds_n;
             total += cnt;
             if (cnt > FT) {
                 // more events than the count or the plan bounded: the records
