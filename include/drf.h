@@ -370,6 +370,42 @@ int drf_prepared_destroy(drf_prepared *p);
 /* Number of device operations in the prepared graph. */
 uint64_t drf_prepared_launches(const drf_prepared *p);
 
+/* Shape-class graph: one hipGraph captured over fixed device buffers for
+ * batches up to the capacities below whose protocols are all statically
+ * small (the planner proves every phase fits one LDS tile, so the check is
+ * device work only: fills, the fused launches, witness picks, results; see
+ * drf_plan.max_phase_records and drf_ctx_get_tuning's tile_events), and
+ * replayed for each new batch of the class.  Same definition and results
+ * as drf_check_batch (Definition 1 per protocol).  The graph is created on
+ * ctx's device with ctx's tuning and owns its buffers (hipMalloc and pinned
+ * staging at creation; none per check). */
+typedef struct {
+    uint32_t max_protocols;   /* protocols of one batch */
+    uint32_t max_nests;       /* unsynchronized leaves times host-unrolled iterations, whole batch */
+    uint32_t max_code_words;  /* compiled leaf code of the whole batch */
+    uint32_t max_fixed;       /* host-unrolled loop values of the whole batch */
+    uint64_t max_phases;      /* phases of the whole batch */
+    uint32_t max_units;       /* fused work units of each evaluator width (at most 2^20) */
+    uint32_t reserved;
+} drf_graph_caps;             /* 32 bytes */
+typedef struct drf_graph drf_graph;
+
+/* DRF_E_ARG for zero or out-of-range capacities, DRF_E_NOMEM, DRF_E_HIP.
+ * stream is unused (reserved). */
+int drf_graph_create(drf_ctx *ctx, const drf_graph_caps *caps, void *stream, drf_graph **out);
+/* Check a batch of the class (arguments, layout and results as
+ * drf_check_batch): plans it on the host, uploads it, replays the graph on
+ * `stream` and copies results and phase counts into the caller's buffers;
+ * returns once that is enqueued (the host waits only for the previous
+ * check's upload).  DRF_E_LIMIT, with nothing written, when the batch is
+ * outside the class (a protocol not statically small, or a capacity
+ * exceeded): use drf_check_batch for it.  Checks of one graph must not
+ * overlap (one host thread, one stream at a time). */
+int drf_graph_check(drf_graph *g, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                    uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
+                    void *stream);
+int drf_graph_destroy(drf_graph *g);
+
 /* Tuning of a context (what the autotuner sets).  tile_events: most access
  * events of one phase (or bucket) sorted in one LDS tile, a power of two in
  * [256, 8192]; digit_bits: the most index bits of one MSD partition level,

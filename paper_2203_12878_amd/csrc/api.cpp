@@ -845,6 +845,18 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     }
 }
 
+// Fused units in launch order: largest first by the power of two of their
+// work, input order within one power (a counting sort, linear in the units).
+std::vector<Unit> order_units(const std::vector<Unit> &units, const std::vector<uint64_t> &work) {
+    auto bucket = [](uint64_t w) { return w ? 64 - __builtin_clzll(w) : 0; };
+    std::vector<size_t> start(66, 0);
+    for (uint64_t w : work) start[65 - bucket(w)]++;
+    for (size_t b = 1; b < start.size(); b++) start[b] += start[b - 1];
+    std::vector<Unit> out(units.size());
+    for (size_t i = 0; i < units.size(); i++) out[start[64 - bucket(work[i])]++] = units[i];
+    return out;
+}
+
 // Profiling off for the duration of one call (an allocation-free call
 // creates no timing events).
 struct ProfOff {
@@ -957,17 +969,10 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         auto fused = [&](std::vector<Unit> &units, bool wide, size_t dst_off, const std::vector<uint64_t> &work,
                          uint64_t events) {
             if (units.empty()) return;
-            // largest first by powers of two of the work, in input order
-            // within one power (a counting sort: linear in the units)
-            auto bucket = [](uint64_t w) { return w ? 64 - __builtin_clzll(w) : 0; };
-            std::vector<size_t> start(66, 0), order(units.size());
-            for (uint64_t w : work) start[65 - bucket(w)]++;
-            for (size_t b = 1; b < start.size(); b++) start[b] += start[b - 1];
-            for (size_t i = 0; i < units.size(); i++) order[start[64 - bucket(work[i])]++] = i;
+            const std::vector<Unit> ord = order_units(units, work);
             for (uint64_t b0 = 0; b0 < units.size(); b0 += CAND_CAP) {
                 const uint64_t n = std::min<uint64_t>(units.size() - b0, CAND_CAP);
-                std::vector<Unit> part(n);
-                for (uint64_t j = 0; j < n; j++) part[j] = units[order[b0 + j]];
+                std::vector<Unit> part(ord.begin() + b0, ord.begin() + b0 + n);
                 const Unit *du = C.put(at<void>(A, dst_off), part);
                 if (qslot >= 64) {
                     C.fill32(qhead, 0, 64 * sizeof(uint32_t));
@@ -1546,6 +1551,234 @@ int drf_run_prepared(drf_prepared *p, void *stream) {
 }
 
 uint64_t drf_prepared_launches(const drf_prepared *p) { return p ? p->rec.ops.size() : 0; }
+
+// ------------------------------------------------------ shape-class graphs
+// A hipGraph captured once over fixed device buffers sized by capacities,
+// replayed for every batch of the class: batches whose protocols are all
+// statically small (their planner bound puts every phase in one LDS tile),
+// so the whole device work is fills, the fused launches, witness picks and
+// results, with no host round trip.  Counts that change from batch to batch
+// (protocols, fused units) are read by the kernels from a header uploaded
+// with the batch.
+struct GraphHdr {
+    uint32_t count;
+    uint32_t nunits[2];
+    uint32_t pad;
+};
+
+struct drf_graph {
+    drf_ctx *priv = nullptr;          // tuning, device, compute units
+    drf_graph_caps caps{};
+    char *dev = nullptr;              // device buffers of the class
+    char *pin = nullptr;              // pinned staging of one batch's upload
+    size_t o_hdr = 0, o_protos = 0, o_nests = 0, o_fixed = 0, o_code = 0, o_units[2] = {0, 0}, o_rin = 0;
+    size_t o_counts = 0, o_results = 0, o_ovf = 0, o_nrec = 0, o_qhead = 0, o_best = 0, o_cand = 0, bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t staged = nullptr;      // the previous batch's upload has been read
+    bool staged_valid = false;
+};
+
+int drf_graph_destroy(drf_graph *g) {
+    if (!g) return DRF_E_ARG;
+    if (g->priv) (void)hipSetDevice(g->priv->device);
+    if (g->staged) {
+        if (g->staged_valid) (void)hipEventSynchronize(g->staged);
+        (void)hipEventDestroy(g->staged);
+    }
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->dev) (void)hipFree(g->dev);
+    if (g->pin) (void)hipHostFree(g->pin);
+    if (g->priv) drf_ctx_destroy(g->priv);
+    delete g;
+    return DRF_OK;
+}
+
+int drf_graph_create(drf_ctx *ctx, const drf_graph_caps *caps, void *stream, drf_graph **out) {
+    if (!ctx || !caps || !out) return DRF_E_ARG;
+    *out = nullptr;
+    const drf_graph_caps c = *caps;
+    if (c.max_protocols == 0 || c.max_units == 0 || c.max_units > CAND_CAP || c.max_phases > (1ull << 40))
+        return DRF_E_ARG;
+    drf_graph *g = new (std::nothrow) drf_graph();
+    if (!g) return DRF_E_NOMEM;
+    g->caps = c;
+    int rc = DRF_OK;
+    hipStream_t cs = nullptr;
+    try {
+        hipck(hipSetDevice(ctx->device));
+        g->priv = new drf_ctx();
+        g->priv->device = ctx->device;
+        g->priv->limit = ctx->limit;
+        g->priv->tune = ctx->tune;
+        g->priv->cus = ctx->cus;
+        if (!ctx_events(g->priv)) throw Fail{DRF_E_HIP};
+        hipck(hipEventCreateWithFlags(&g->staged, hipEventDisableTiming));
+        // uploaded part first (one staging image), then the device-only part
+        Bump b;
+        g->o_hdr = b.reserve(sizeof(GraphHdr));
+        g->o_protos = b.reserve((size_t)c.max_protocols * sizeof(ProtoDesc));
+        g->o_nests = b.reserve((size_t)c.max_nests * sizeof(NestDesc));
+        g->o_fixed = b.reserve((size_t)c.max_fixed * sizeof(FixedVal));
+        g->o_code = b.reserve((size_t)c.max_code_words * sizeof(uint32_t));
+        g->o_units[0] = b.reserve((size_t)c.max_units * sizeof(Unit));
+        g->o_units[1] = b.reserve((size_t)c.max_units * sizeof(Unit));
+        g->o_rin = b.reserve((size_t)c.max_protocols * sizeof(ResultIn));
+        const size_t staged_bytes = b.used;
+        g->o_counts = b.reserve(std::max<uint64_t>(1, c.max_phases) * sizeof(uint64_t));
+        g->o_results = b.reserve((size_t)c.max_protocols * sizeof(drf_result));
+        g->o_ovf = b.reserve((size_t)c.max_protocols * sizeof(uint32_t));
+        g->o_nrec = b.reserve((size_t)c.max_protocols * sizeof(uint64_t));
+        g->o_qhead = b.reserve(64 * sizeof(uint32_t));
+        g->o_best = b.reserve((size_t)c.max_protocols * sizeof(Best));
+        g->o_cand = b.reserve((size_t)c.max_units * sizeof(Cand));
+        g->bytes = b.used + ALIGN;
+        if (hipMalloc((void **)&g->dev, g->bytes) != hipSuccess) {
+            g->dev = nullptr;
+            (void)hipGetLastError();
+            throw Fail{DRF_E_NOMEM};
+        }
+        if (hipHostMalloc((void **)&g->pin, staged_bytes + ALIGN, hipHostMallocDefault) != hipSuccess) {
+            g->pin = nullptr;
+            (void)hipGetLastError();
+            throw Fail{DRF_E_NOMEM};
+        }
+        char *D = g->dev;
+        const GraphHdr *hdr = (const GraphHdr *)(D + g->o_hdr);
+        const ProtoDesc *dprotos = (const ProtoDesc *)(D + g->o_protos);
+        const NestDesc *dnests = (const NestDesc *)(D + g->o_nests);
+        const FixedVal *dfixed = (const FixedVal *)(D + g->o_fixed);
+        const uint32_t *dcode = (const uint32_t *)(D + g->o_code);
+        unsigned long long *counts = (unsigned long long *)(D + g->o_counts);
+        unsigned long long *nrec = (unsigned long long *)(D + g->o_nrec);
+        uint32_t *ovf = (uint32_t *)(D + g->o_ovf);
+        uint32_t *qhead = (uint32_t *)(D + g->o_qhead);
+        Best *best = (Best *)(D + g->o_best);
+        Cand *cand = (Cand *)(D + g->o_cand);
+        const ResultIn *rin = (const ResultIn *)(D + g->o_rin);
+        drf_result_dev *res = (drf_result_dev *)(D + g->o_results);
+        hipck(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        FillList L{};
+        auto add = [&](void *p, uint32_t v, size_t bytes) {
+            L.p[L.count] = (uint32_t *)p;
+            L.v[L.count] = v;
+            L.n[L.count] = bytes / 4;
+            L.count++;
+        };
+        add(counts, 0u, std::max<uint64_t>(1, c.max_phases) * sizeof(uint64_t));
+        add(ovf, 0u, (size_t)c.max_protocols * sizeof(uint32_t));
+        add(best, 0xFFFFFFFFu, (size_t)c.max_protocols * sizeof(Best));
+        add(nrec, 0u, (size_t)c.max_protocols * sizeof(uint64_t));
+        add(qhead, 0u, 64 * sizeof(uint32_t));
+        hipError_t e = launch_fill_multi(L, cs);
+        const uint32_t grid = g->priv->cus * 2, tile = small_events(g->priv);
+        for (int w = 0; w < 2 && e == hipSuccess; w++) {
+            const Unit *du = (const Unit *)(D + g->o_units[w]);
+            e = launch_fused(du, c.max_units, qhead + w, w == 1, dnests, dprotos, dfixed, dcode, counts, nrec, ovf,
+                             cand, best, grid, tile, cs, &hdr->nunits[w]);
+            if (e == hipSuccess) e = launch_pick(cand, c.max_units, best, cs, &hdr->nunits[w]);
+        }
+        if (e == hipSuccess) e = launch_result(c.max_protocols, rin, best, nrec, ovf, res, cs, &hdr->count);
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+        g->graph = gr;
+        if (e != hipSuccess || e2 != hipSuccess || !gr) throw Fail{DRF_E_HIP};
+        hipck(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        // one replay on the caller's stream initializes nothing the runs rely
+        // on; the class is ready
+        (void)stream;
+    } catch (Fail f) {
+        rc = f.code;
+    } catch (...) {
+        rc = DRF_E_NOMEM;
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != DRF_OK) {
+        (void)hipGetLastError();
+        drf_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return DRF_OK;
+}
+
+int drf_graph_check(drf_graph *g, const uint32_t *code, const uint64_t *code_off, const uint32_t *nthreads,
+                    uint32_t count, drf_result *d_results, uint64_t *d_phase_counts, uint64_t phase_cap,
+                    void *stream) {
+    if (!g || !code_off || !nthreads || (count && (!code || !d_results))) return DRF_E_ARG;
+    if (count == 0) return DRF_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    try {
+        hipck(hipSetDevice(g->priv->device));
+        Call C;
+        C.ctx = g->priv;
+        C.st = st;
+        C.count = count;
+        C.keep.ctx = g->priv;
+        C.plan_all(code, code_off, nthreads);
+        C.build_blob();
+        // the class: statically small protocols within the capacities
+        for (uint32_t i = 0; i < count; i++)
+            if (C.status[i] == 0 && !C.stat[i]) return DRF_E_LIMIT;
+        const drf_graph_caps &c = g->caps;
+        if (count > c.max_protocols || C.nests.size() > c.max_nests || C.code.size() > c.max_code_words ||
+            C.fixed.size() > c.max_fixed || C.total_phases > c.max_phases || C.sunits[0].size() > c.max_units ||
+            C.sunits[1].size() > c.max_units)
+            return DRF_E_LIMIT;
+        if (C.total_phases > phase_cap || (C.total_phases && !d_phase_counts)) return DRF_E_ARG;
+        // the upload, staged at the device offsets: header, blob, units
+        // (largest first, as in a direct check), result inputs
+        if (g->staged_valid) hipck(hipEventSynchronize(g->staged));
+        char *P = g->pin;
+        GraphHdr h{count, {0, 0}, 0};
+        std::vector<std::pair<size_t, size_t>> parts;
+        auto stage = [&](size_t off, const void *src, size_t bytes) {
+            if (!bytes) return;
+            memcpy(P + off, src, bytes);
+            parts.push_back({off, bytes});
+        };
+        for (int w = 0; w < 2; w++) {
+            std::vector<Unit> &us = C.sunits[w];
+            std::vector<uint64_t> work(us.size());
+            for (size_t j = 0; j < us.size(); j++) work[j] = (us[j].k1 - us[j].k0) * C.plans[us[j].proto].max_phase_records;
+            std::vector<Unit> ord = order_units(us, work);
+            h.nunits[w] = (uint32_t)ord.size();
+            stage(g->o_units[w], ord.data(), ord.size() * sizeof(Unit));
+        }
+        std::vector<ResultIn> rin(count);
+        for (uint32_t i = 0; i < count; i++) {
+            rin[i].status = C.status[i];
+            rin[i].num_phases = C.status[i] ? 0 : (uint32_t)C.protos[i].nphases;
+            rin[i].num_records = 0;
+            rin[i].flags = C.status[i] == 0 ? RESULT_FROM_DEVICE : 0;
+        }
+        stage(g->o_hdr, &h, sizeof h);
+        stage(g->o_protos, C.protos.data(), C.protos.size() * sizeof(ProtoDesc));
+        stage(g->o_nests, C.nests.data(), C.nests.size() * sizeof(NestDesc));
+        stage(g->o_fixed, C.fixed.data(), C.fixed.size() * sizeof(FixedVal));
+        stage(g->o_code, C.code.data(), C.code.size() * sizeof(uint32_t));
+        stage(g->o_rin, rin.data(), rin.size() * sizeof(ResultIn));
+        for (auto &pt : parts)
+            hipck(hipMemcpyAsync(g->dev + pt.first, P + pt.first, pt.second, hipMemcpyHostToDevice, st));
+        hipck(hipEventRecord(g->staged, st));
+        g->staged_valid = true;
+        hipck(hipGraphLaunch(g->exec, st));
+        hipck(hipMemcpyAsync(d_results, g->dev + g->o_results, (size_t)count * sizeof(drf_result),
+                             hipMemcpyDeviceToDevice, st));
+        if (C.total_phases)
+            hipck(hipMemcpyAsync(d_phase_counts, g->dev + g->o_counts, C.total_phases * sizeof(uint64_t),
+                                 hipMemcpyDeviceToDevice, st));
+        return DRF_OK;
+    } catch (Fail f) {
+        (void)hipGetLastError();
+        return f.code;
+    } catch (...) {
+        return DRF_E_NOMEM;
+    }
+}
 
 int drf_babycuda_infer(const char *text, size_t len, const char *params, char *out, size_t cap, size_t *needed,
                        int32_t *status) {

@@ -1520,7 +1520,8 @@ DEV uint32_t block_excl_sat(uint32_t v, uint32_t *red, uint32_t &total) {
 }
 
 template <typename T, bool WIDE, uint32_t FT = TILE>
-DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,
+DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, const uint32_t *__restrict__ nunits_dev,
+                    uint32_t *__restrict__ qhead,
                     const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,
                     const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
                     unsigned long long *__restrict__ phase_counts, unsigned long long *__restrict__ nrec,
@@ -1539,6 +1540,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
     __shared__ FusedStage lds_st;
     __shared__ FastLds lds_fx;
     unsigned long long *nf = lds_nf[threadIdx.x >> 6];
+    if (nunits_dev) nunits = *nunits_dev;   // a graph replay: the count of this run
     // persistent: workgroups pull units (largest first) from a device queue
     for (;;) {
         if (threadIdx.x == 0) {
@@ -2038,12 +2040,14 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, uint32_t *_
 }
 
 #define FUSED_PARAMS                                                                                    \
-    const Unit *__restrict__ units, uint32_t nunits, uint32_t *__restrict__ qhead,                       \
+    const Unit *__restrict__ units, uint32_t nunits, const uint32_t *__restrict__ nunits_dev,            \
+        uint32_t *__restrict__ qhead,                                                                   \
         const NestDesc *__restrict__ nests, const ProtoDesc *__restrict__ protos,                       \
         const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,                          \
         unsigned long long *__restrict__ phase_counts, unsigned long long *__restrict__ nrec,           \
         uint32_t *__restrict__ ovf_flags, Cand *__restrict__ cands, Best *__restrict__ best, uint32_t tile
-#define FUSED_ARGS units, nunits, qhead, nests, protos, fixed, code, phase_counts, nrec, ovf_flags, cands, best, tile
+#define FUSED_ARGS \
+    units, nunits, nunits_dev, qhead, nests, protos, fixed, code, phase_counts, nrec, ovf_flags, cands, best, tile
 // 32-bit evaluator: two workgroups per CU fit the LDS, so ask for the
 // registers of two waves per SIMD.  The 64-bit one keeps its natural
 // allocation (bounding it would spill).
@@ -2294,18 +2298,21 @@ __global__ void k_single3(const Group *__restrict__ groups, uint32_t ngroups, co
 }
 
 // ==================================================== witness pair pick
-__global__ void k_pick(const Cand *__restrict__ cands, uint64_t n, Best *__restrict__ best) {
+__global__ void k_pick(const Cand *__restrict__ cands, uint64_t n, const uint32_t *__restrict__ n_dev,
+                       Best *__restrict__ best) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n_dev) n = *n_dev;
     if (i >= n) return;
     const Cand c = cands[i];
     if (c.key != ~0ull && c.key == best[c.proto].key) best[c.proto].pair = c.pair;
 }
 
 // ================================================================ results
-__global__ void k_result(uint32_t count, const ResultIn *__restrict__ rin, const Best *__restrict__ best,
-                         const unsigned long long *__restrict__ nrec, const uint32_t *__restrict__ ovf_flags,
-                         drf_result_dev *__restrict__ out) {
+__global__ void k_result(uint32_t count, const uint32_t *__restrict__ count_dev, const ResultIn *__restrict__ rin,
+                         const Best *__restrict__ best, const unsigned long long *__restrict__ nrec,
+                         const uint32_t *__restrict__ ovf_flags, drf_result_dev *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (count_dev) count = *count_dev;
     if (i >= count) return;
     ResultIn r = rin[i];
     if (r.flags & RESULT_FROM_DEVICE) {
@@ -2393,13 +2400,16 @@ hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const Nest
 hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, bool wide, const NestDesc *nests,
                         const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
                         unsigned long long *phase_counts, unsigned long long *nrec, uint32_t *ovf_flags,
-                        Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s) {
+                        Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s,
+                        const uint32_t *nunits_dev) {
+    // with nunits_dev the count is read on the device and nunits bounds it
     const uint32_t g = nunits < grid ? nunits : grid;
+    if (g == 0) return hipSuccess;
     if (wide)
-        return launch(k_fused64, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed, code, phase_counts,
-                      nrec, ovf_flags, cands, best, tile);
-    return launch(k_fused32, dim3(g), dim3(WG), s, units, nunits, qhead, nests, protos, fixed, code, phase_counts,
-                  nrec, ovf_flags, cands, best, tile);
+        return launch(k_fused64, dim3(g), dim3(WG), s, units, nunits, nunits_dev, qhead, nests, protos, fixed, code,
+                      phase_counts, nrec, ovf_flags, cands, best, tile);
+    return launch(k_fused32, dim3(g), dim3(WG), s, units, nunits, nunits_dev, qhead, nests, protos, fixed, code,
+                  phase_counts, nrec, ovf_flags, cands, best, tile);
 }
 
 hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
@@ -2435,8 +2445,10 @@ hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned l
 }
 
 hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, const unsigned long long *nrec,
-                         const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s) {
-    return launch(k_result, dim3((count + 255) / 256), dim3(256), s, count, rin, best, nrec, ovf_flags, out);
+                         const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s, const uint32_t *count_dev) {
+    if (count == 0) return hipSuccess;
+    return launch(k_result, dim3((count + 255) / 256), dim3(256), s, count, count_dev, rin, best, nrec, ovf_flags,
+                  out);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {
@@ -2467,8 +2479,9 @@ hipError_t launch_init_acc(SingleAcc *a, uint32_t n, hipStream_t s) {
     return launch(k_init_acc, dim3((n + 255) / 256), dim3(256), s, a, n);
 }
 
-hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s) {
-    return launch(k_pick, dim3((uint32_t)((ncands + 255) / 256)), dim3(256), s, cands, ncands, best);
+hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s, const uint32_t *n_dev) {
+    if (ncands == 0) return hipSuccess;
+    return launch(k_pick, dim3((uint32_t)((ncands + 255) / 256)), dim3(256), s, cands, ncands, n_dev, best);
 }
 
 // ------------------------------------------------ fixed scratch array

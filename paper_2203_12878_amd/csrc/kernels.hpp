@@ -74,7 +74,8 @@ hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const Nest
 hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, bool wide, const NestDesc *nests,
                         const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
                         unsigned long long *phase_counts, unsigned long long *nrec, uint32_t *ovf_flags,
-                        Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s);
+                        Cand *cands, Best *best, uint32_t grid, uint32_t tile, hipStream_t s,
+                        const uint32_t *nunits_dev = nullptr);
 
 hipError_t launch_hist(const Seg *segs, const Chunk *chunks, uint32_t nchunks, const unsigned long long *in,
                        unsigned long long *hist, hipStream_t s);
@@ -92,7 +93,10 @@ hipError_t launch_tiles(const Tile *tiles, uint32_t ntiles, const unsigned long 
 hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned long long *recs,
                          SingleAcc *acc, Cand *cands, Best *best, hipStream_t s);
 
-hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s);
+// (n_dev / count_dev / nunits_dev: counts read on the device, for graph
+// replays; the host count then bounds the grid)
+hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s,
+                       const uint32_t *n_dev = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
 
 // Up to FILL_MAX word fills in one launch (passed by value).
@@ -131,7 +135,8 @@ struct ResultIn {
 };
 
 hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, const unsigned long long *nrec,
-                         const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s);
+                         const uint32_t *ovf_flags, drf_result_dev *out, hipStream_t s,
+                         const uint32_t *count_dev = nullptr);
 
 // Bytes of the per-device scratch array of the allocation-free checking
 // call (a file-scope device array in kernels.hip, held until the process

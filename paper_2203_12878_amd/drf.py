@@ -38,6 +38,12 @@ class Plan(ctypes.Structure):
                 ("max_phase_records", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64)]
 
 
+class GraphCaps(ctypes.Structure):
+    _fields_ = [("max_protocols", ctypes.c_uint32), ("max_nests", ctypes.c_uint32),
+                ("max_code_words", ctypes.c_uint32), ("max_fixed", ctypes.c_uint32),
+                ("max_phases", ctypes.c_uint64), ("max_units", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_events", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32),
                 ("unit_events", ctypes.c_uint32), ("item_events", ctypes.c_uint32)]
@@ -82,6 +88,12 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.drf_check_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.drf_graph_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(GraphCaps), ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.drf_graph_check.argtypes = L.drf_check_batch.argtypes
+        L.drf_graph_destroy.argtypes = [ctypes.c_void_p]
+        for f in ("drf_graph_create", "drf_graph_check", "drf_graph_destroy"):
+            getattr(L, f).restype = ctypes.c_int
         L.drf_check_batch_noalloc.argtypes = L.drf_check_batch.argtypes
         L.drf_check_batch_noalloc.restype = ctypes.c_int
         L.drf_prepare_batch.argtypes = [ctypes.c_void_p, u32p, u64p, u32p, ctypes.c_uint32, ctypes.c_void_p,
@@ -349,6 +361,43 @@ class Prepared:
             pass
 
 
+class GraphClass:
+    """A hipGraph captured once for a shape class of statically small
+    batches (drf_graph_create); check() replays it for a new batch, or
+    returns False when the batch is outside the class (nothing written)."""
+
+    def __init__(self, chk: "Checker", max_protocols: int = 256, max_nests: int = 8192,
+                 max_code_words: int = 1 << 18, max_fixed: int = 8192, max_phases: int = 1 << 20,
+                 max_units: int = 1 << 16):
+        self.caps = GraphCaps(max_protocols, max_nests, max_code_words, max_fixed, max_phases, max_units, 0)
+        self._h = ctypes.c_void_p()
+        self._stream = chk._stream
+        rc = lib().drf_graph_create(chk._ctx, ctypes.byref(self.caps), None, ctypes.byref(self._h))
+        if rc != OK:
+            raise DrfError(rc, "drf_graph_create")
+
+    def check(self, b: Batch, stream=None) -> bool:
+        rc = lib().drf_graph_check(self._h, _u32p(b.code), _u64p(b.code_off), _u32p(b.nthreads), b.count,
+                                   ctypes.c_void_p(b.results.data_ptr()), ctypes.c_void_p(b.counts.data_ptr()),
+                                   b.total_phases, self._stream(stream))
+        if rc == E_LIMIT:
+            return False
+        if rc != OK:
+            raise DrfError(rc, "drf_graph_check")
+        return True
+
+    def close(self):
+        if self._h:
+            lib().drf_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Checker:
     """Owns a libdrf context on one HIP device (one per host thread)."""
 
@@ -466,6 +515,10 @@ class Checker:
             raise DrfError(rc, "drf_check_arrays")
         (stream or torch.cuda.current_stream(self.device)).synchronize()
         return o.collect()
+
+    def graph_class(self, **caps) -> GraphClass:
+        """A shape-class graph for statically small batches (drf_graph_create)."""
+        return GraphClass(self, **caps)
 
     def prepare(self, b: Batch, stream=None) -> Prepared:
         """Check `b` once and capture the device work as one hipGraph."""

@@ -1,6 +1,9 @@
-"""Prepared batches (one hipGraph per batch): every replay reproduces the
-oracle's results exactly, with eager checks and synchronizations between
-the replays; the autotuner's tunings keep results equal to the oracle's."""
+"""Graphs: a prepared batch (one hipGraph per batch) reproduces the
+oracle's results on every replay, with eager checks and synchronizations
+between the replays; a shape-class graph (captured once) checks several
+different statically small batches exactly as the oracle does and refuses
+batches outside its class without writing anything; the autotuner's
+tunings keep results equal to the oracle's."""
 import pytest
 
 from oracle import o2
@@ -54,3 +57,46 @@ def test_tunings_keep_results_exact(tune):
     got = chk.check_batch(items)
     chk.close()
     assert [r.key() for r in got] == [r.key() for r in ref]
+
+
+def _static_items():
+    from paper_2203_12878_amd import drf
+    mixed = [(t, n) for t, n, _ in w.gen_mixed_batch(2, 300)]
+    mixed = [it for it in mixed if drf.plan(*it).max_phase_records <= 8192][:120]
+    items = [w.gen_small(s) for s in range(4)]
+    items += [w.tree_protocol(k, r) for k, r in ((8, None), (9, 3), (10, 9), (11, 0), (11, None))]
+    items += [("(seq (if (= tid 0) (wr 1) (wr 2)) (sync) (if (= tid 1) (rd 0) (skip)) (wr 0))", 2),
+              ("(foru x 0 3 (seq (wr 5) (rd (+ tid x))))", 900), ("(wr (<< 1 tid))", 40), ("(rd x)", 4)]
+    return items + mixed
+
+
+def test_graph_class_replays_new_batches_like_the_oracle():
+    import torch
+    from paper_2203_12878_amd import drf
+    chk = drf.Checker(0)
+    gc = chk.graph_class(max_protocols=160, max_nests=8192, max_code_words=1 << 18, max_fixed=8192,
+                         max_phases=1 << 20, max_units=1 << 16)
+    items = _static_items()
+    want_all = o2.check_many(items, jobs=16)
+    # batches of different sizes and contents through the one captured graph
+    n = len(items)
+    batches = [list(range(n)), list(range(40, 90)), list(range(9)), list(range(129, 4, -1)), list(range(100, n))]
+    for bi, idx in enumerate(batches):
+        its = [items[i] for i in idx]
+        want = [want_all[i] for i in idx]
+        b = drf.Batch(its, 0)
+        assert gc.check(b), bi
+        torch.cuda.synchronize()
+        assert [r.key() for r in b.collect()] == [r.key() for r in want], bi
+        # eager work between replays
+        again = chk.check_batch(its[:3])
+        assert [r.key() for r in again] == [r.key() for r in want[:3]]
+    # outside the class: a phase above one tile, or more protocols than the capacity
+    for its in ([w.tree_protocol(14, None)] + items[:4], items + items[:50]):
+        b = drf.Batch(its, 0)
+        b.results.fill_(7)
+        assert not gc.check(b)
+        torch.cuda.synchronize()
+        assert int(b.results.min()) == 7 and int(b.results.max()) == 7
+    gc.close()
+    chk.close()
