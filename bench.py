@@ -145,6 +145,61 @@ def parity(results, gname: str):
                            e["phase_counts_sha256"])) for r, e in zip(results, exp))
 
 
+def parity_subset(results, gname: str, idx):
+    """Results of the protocols idx of a stored workload against its stored
+    oracle results."""
+    path = os.path.join(GOLDEN, "expected_%s.json" % gname)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        exp = json.load(f)["results"]
+    sub = [exp[i] for i in idx]
+    return len(sub) == len(results) and all(
+        [r.status, r.racy, list(r.witness) if r.witness else None, r.num_records] ==
+        [e["status"], e["racy"], e["witness"], e["num_records"]] and
+        (r.status != 0 or (len(r.phase_counts) == e["num_phases"] and counts_sha(r.phase_counts) ==
+                           e["phase_counts_sha256"])) for r, e in zip(results, sub))
+
+
+def graph_leg(drf, chk, steps):
+    """Shape-class graph against the direct batched call on the statically
+    small protocols of the mixed batch: the whole subset as one batch, and
+    batches of 8 (where launch overhead matters), both with parity."""
+    import torch
+    items, _, _ = workload("mixed", 0)
+    tile = chk.tuning()["tile_events"]
+    all_plans, _ = drf.plan_batch(items, chk)
+    idx = [i for i, p in enumerate(all_plans) if p.status == 0 and p.max_phase_records <= tile]
+    sub = [items[i] for i in idx]
+    plans = [all_plans[i] for i in idx]
+    phases = sum(p.num_phases for p in plans)
+    gc = chk.graph_class(max_protocols=len(sub), max_nests=1 << 20, max_code_words=1 << 22, max_fixed=1 << 20,
+                         max_phases=phases, max_units=1 << 20)
+    out = {"protocols": len(sub)}
+    b = drf.Batch(sub, 0, plans=plans)
+    for name, run in (("direct", lambda bb: chk.run_batch(bb)), ("graph", lambda bb: gc.check(bb))):
+        secs, _ = timed(run, b, steps, 1)
+        res = b.collect()
+        out[name + "_records_per_s"] = round(sum(r.num_records for r in res) / secs, 1)
+        out[name + "_ms"] = round(secs * 1e3, 3)
+        out["parity_" + name] = parity_subset(res, "mixed", idx)
+    small = [drf.Batch(sub[j:j + 8], 0, plans=plans[j:j + 8]) for j in range(0, 64, 8)]
+    for name, run in (("direct", lambda bb: chk.run_batch(bb)), ("graph", lambda bb: gc.check(bb))):
+        for bb in small:
+            run(bb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            for bb in small:
+                run(bb)
+                torch.cuda.synchronize()
+        out["batch8_" + name + "_ms"] = round((time.perf_counter() - t0) / (5 * len(small)) * 1e3, 4)
+        res = [r for bb in small for r in bb.collect()]
+        out["batch8_parity_" + name] = parity_subset(res, "mixed", idx[:64])
+    gc.close()
+    return out
+
+
 def timed(run, batch, steps, warmup, lib=None, ctx=None):
     """Warm-up runs, then `steps` timed runs bracketed by device syncs.
     Returns (seconds per step, per-kernel stats of the timed runs)."""
@@ -240,7 +295,7 @@ def serving(drf, rates):
         rows.append({"offered_req_per_s": rate, "requests": len(reqs), "p50_ms": round(st.percentile(50) * 1e3, 3),
                      "p99_ms": round(st.percentile(99) * 1e3, 3), "records_per_s": round(recs / wall, 1),
                      "req_per_s": round(len(reqs) / wall, 1), "batches": st.batches,
-                     "max_in_flight_bytes": st.max_in_flight_bytes,
+                     "max_in_flight_bytes": st.max_in_flight_bytes, "graph_batches": st.graph_batches,
                      "parity_vs_oracle": parity(res, "serve%dk" % (rate // 1000)),
                      "parity_vs_alone": all(a.key() == m.key() for a, m in zip(alone, res))})
     alone_chk.close()
@@ -383,6 +438,7 @@ def main():
                          "effective_hbm_frac": round(lrec / lsecs * EFFECTIVE_BYTES_PER_RECORD /
                                                      (HBM_PEAK_GBS * 1e9), 4),
                          "kernels": per_kernel(lstats, max(3, args.steps))}
+        line["graph"] = graph_leg(drf, chk, args.steps)
         line["serving"] = serving(drf, [1000, 5000, 20000, 50000])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(items)

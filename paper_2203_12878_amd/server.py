@@ -17,6 +17,10 @@ context's limit).
 
 Requests that arrive while batches run are admitted as soon as memory and
 a worker free up, and batches of different workers overlap on the device.
+A batch whose protocols are all statically small (every phase fits one
+LDS tile by the plan) and that fits the worker's shape class is checked by
+replaying the worker's class graph (one hipGraph launch, no host round
+trip); any other batch goes through drf_check_batch.
 Results stay in device memory until the batch completes; latency is
 measured from submit() to the result.  A request whose future was
 cancelled before admission is dropped; submit() raises Overloaded when the
@@ -43,6 +47,9 @@ from . import drf
 # scratch a worker's context keeps between batches (pool A of a typical
 # batch: metadata and witness candidates)
 RETAIN_BYTES = 64 << 20
+# shape class of each worker's graph (batches beyond it use drf_check_batch)
+GRAPH_CAPS = dict(max_protocols=256, max_nests=16384, max_code_words=1 << 18, max_fixed=16384,
+                  max_phases=1 << 21, max_units=1 << 16)
 
 
 class Overloaded(RuntimeError):
@@ -69,6 +76,7 @@ class Stats:
     batches: int = 0
     max_batch_size: int = 0
     max_in_flight_bytes: int = 0      # largest sum of footprints held at once
+    graph_batches: int = 0            # batches checked by a class graph replay
     latencies: List[float] = field(default_factory=list)
 
     def percentile(self, q: float) -> float:
@@ -99,7 +107,7 @@ def admit(queue: Sequence[Request], call_bytes: int, free_bytes: int, in_flight:
 
 class Server:
     def __init__(self, device: int = 0, workers: int = 2, budget_bytes: int = 16 << 30,
-                 max_batch: int = 4096, max_queue: int = 1 << 20):
+                 max_batch: int = 4096, max_queue: int = 1 << 20, graph_caps: Optional[dict] = None):
         import torch
         self.device = device
         self.budget = int(budget_bytes)
@@ -115,6 +123,9 @@ class Server:
         self._threads = []
         self._checkers = []
         self._streams = []
+        self._graphs = []
+        # shape class of the workers' graphs (None: no graphs)
+        self.graph_caps = dict(GRAPH_CAPS) if graph_caps is None else (graph_caps or None)
         # per-call scratch (what a check of the smallest protocol takes):
         # charged once per batch, not per request
         self.call_bytes = int(drf.plan("(skip)", 1).scratch_bytes)
@@ -123,6 +134,7 @@ class Server:
             chk = drf.Checker(device, scratch_limit=max(self.budget, 2 * self.call_bytes))
             self._checkers.append(chk)
             self._streams.append(torch.cuda.Stream(device=device))
+            self._graphs.append(chk.graph_class(**self.graph_caps) if self.graph_caps else None)
         for w in range(workers):
             t = threading.Thread(target=self._worker, args=(w,), daemon=True)
             t.start()
@@ -167,6 +179,9 @@ class Server:
             self._cv.notify_all()
         for t in self._threads:
             t.join()
+        for gr in self._graphs:
+            if gr is not None:
+                gr.close()
         for c in self._checkers:
             c.close()
 
@@ -218,6 +233,8 @@ class Server:
         import torch
         chk = self._checkers[w]
         stream = self._streams[w]
+        graph = self._graphs[w]
+        tile = chk.tuning()["tile_events"]
         while True:
             got = self._take()
             if got is None:
@@ -229,10 +246,15 @@ class Server:
             try:
                 with torch.cuda.stream(stream):
                     b = drf.Batch([(r.code, r.n) for r in batch], self.device, plans=[r.plan for r in batch])
-                    chk.run_batch(b, stream)
+                    static = graph is not None and len(batch) <= graph.caps.max_protocols and all(
+                        r.plan.status != 0 or r.plan.max_phase_records <= tile for r in batch)
+                    by_graph = static and graph.check(b, stream)
+                    if not by_graph:
+                        chk.run_batch(b, stream)
                     stream.synchronize()
                     res = b.collect()
-                    chk.release(RETAIN_BYTES)
+                    if not by_graph:
+                        chk.release(RETAIN_BYTES)
             except Exception as e:  # a failed batch fails its requests, not the server
                 self._finish(held)
                 for r in batch:
@@ -243,6 +265,7 @@ class Server:
             with self._cv:
                 st = self.stats
                 st.batches += 1
+                st.graph_batches += 1 if by_graph else 0
                 st.max_batch_size = max(st.max_batch_size, len(batch))
                 for r, x in zip(batch, res):
                     r.t_done = now

@@ -2,7 +2,9 @@
 mix equals its result checked alone (exact integers, tolerance 0), the
 oracle agrees on the smaller ones, admission keeps the footprints held at
 once within the one device-wide budget, cancelled requests never run and a
-full queue refuses new requests."""
+full queue refuses new requests.  The stream is served both with the
+workers' class graphs (statically small batches replayed as one graph
+launch) and without them."""
 import pytest
 
 from oracle import o2
@@ -11,18 +13,20 @@ from paper_2203_12878_amd import workloads as w
 pytestmark = pytest.mark.gpu
 
 
-def test_serving_mix_equals_alone():
+@pytest.mark.parametrize("graphs", [True, False])
+def test_serving_mix_equals_alone(graphs):
     from paper_2203_12878_amd import drf
     from paper_2203_12878_amd.server import Server, run_stream
     reqs = w.gen_requests(rate=3000.0, max_requests=400, horizon_s=1.0)
     assert len(reqs) > 100
     budget = 2 << 30
-    with Server(device=0, workers=2, budget_bytes=budget) as srv:
+    with Server(device=0, workers=2, budget_bytes=budget, graph_caps=None if graphs else {}) as srv:
         mixed, wall = run_stream(srv, reqs)
         st = srv.stats
     assert st.completed == len(reqs)
     assert st.batches < len(reqs)          # requests were batched
     assert st.max_in_flight_bytes <= budget   # a request above the budget runs alone
+    assert (st.graph_batches > 0) == graphs
     chk = drf.Checker(0)
     alone = [chk.check(t, n) for _, t, n, _ in reqs]
     chk.close()
