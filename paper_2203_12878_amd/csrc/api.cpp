@@ -1123,14 +1123,17 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         // ---- big phases, in waves under the scratch budget
         if (!big.empty()) {
             const uint64_t a_end = (C.needA + ALIGN - 1) & ~(ALIGN - 1);
-            const uint64_t budget = noalloc ? (FIXED_SCRATCH_BYTES > a_end ? FIXED_SCRATCH_BYTES - a_end : 0)
-                                            : (ctx->limit > ctx->sizeA ? ctx->limit - ctx->sizeA : 0);
+            uint64_t budget = noalloc ? (FIXED_SCRATCH_BYTES > a_end ? FIXED_SCRATCH_BYTES - a_end : 0)
+                                      : (ctx->limit > ctx->sizeA ? ctx->limit - ctx->sizeA : 0);
+            std::vector<Wave> waves;
+            size_t needB = 0;
+            const std::vector<int32_t> status0 = C.status;
+            for (int shrink = 0;; shrink++) {
+            C.status = status0;
             // records per wave: about 21 bytes of pool B per record (two
             // record buffers and the partition metadata); the cap shrinks
             // until the largest wave's layout fits the budget
             uint64_t rec_cap = budget / 24;
-            std::vector<Wave> waves;
-            size_t needB = 0;
             for (int attempt = 0;; attempt++) {
                 waves.clear();
                 std::vector<int32_t> st_try = C.status;
@@ -1182,9 +1185,20 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             if (noalloc) {
                 if (needB > budget) throw Fail{DRF_E_NOMEM};
                 C.B = (char *)ctx->fixed + a_end;
-            } else {
+                break;
+            }
+            try {
                 grow(ctx, ctx->poolB, ctx->sizeB, needB, st);
-                C.B = ctx->poolB;
+            } catch (Fail f) {
+                // the device could not give a pool this large, although it
+                // is within the limit: plan smaller waves
+                if (f.code != DRF_E_NOMEM || shrink == 6 || needB <= (256ull << 20)) throw;
+                C.tr.mark("pool B allocation failed", needB);
+                budget = needB / 2;
+                continue;
+            }
+            C.B = ctx->poolB;
+            break;
             }
             C.tr.mark("waves planned", waves.size());
             for (const Wave &W : waves) run_wave(C, big, W, best, cand);
