@@ -161,6 +161,29 @@ def parity_subset(results, gname: str, idx):
                            e["phase_counts_sha256"])) for r, e in zip(results, sub))
 
 
+def table_ab(drf, chk, steps, lib):
+    """The sort-free table path for dense big phases against the partition
+    path on the whole mixed and tree batches (same tuning otherwise), both
+    with parity against the stored oracle results."""
+    out = {}
+    for name, bits in (("mixed", 20), ("tree", 24)):
+        items, wl, _ = workload(name, 0)
+        b = drf.Batch(items, 0)
+        row = {"table_bits": bits}
+        for leg, tb in (("partition", drf.TABLE_OFF), ("table", bits)):
+            chk.set_tuning(table_bits=tb)
+            secs, st = timed(chk.run_batch, b, steps, 1, lib, chk._ctx)
+            res = b.collect()
+            row[leg + "_ms"] = round(secs * 1e3, 3)
+            row[leg + "_records_per_s"] = round(sum(r.num_records for r in res) / secs, 1)
+            row[leg + "_parity"] = parity(res, wl)
+            row[leg + "_kernels"] = {k: [round(v["ms_per_step"], 3), v["records_per_step"]]
+                                     for k, v in per_kernel(st, steps).items()}
+        chk.set_tuning(table_bits=drf.TABLE_OFF)
+        out[name] = row
+    return out
+
+
 def graph_leg(drf, chk, steps):
     """Shape-class graph against the direct batched call on the statically
     small protocols of the mixed batch: the whole subset as one batch, and
@@ -369,6 +392,7 @@ def main():
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--unit-events", type=int, default=0)
     ap.add_argument("--item-events", type=int, default=0)
+    ap.add_argument("--table-bits", type=int, default=0, help="table path for big phases (255: off)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -395,7 +419,7 @@ def main():
     elif not args.no_tuning_cache and autotune.apply_cached(chk, batch, cache_path=cache):
         tuning_source = "autotuner cache (%s)" % autotune.size_class(batch)
     chk.set_tuning(tile_events=args.tile_events, digit_bits=args.digit_bits, unit_events=args.unit_events,
-                   item_events=args.item_events)
+                   item_events=args.item_events, table_bits=args.table_bits)
     run = chk.run_plain if path == "plain" else chk.run_batch
     secs, stats = timed(run, batch, args.steps, args.warmup, lib, chk._ctx)
     results = batch.collect()
@@ -439,6 +463,7 @@ def main():
                                                      (HBM_PEAK_GBS * 1e9), 4),
                          "kernels": per_kernel(lstats, max(3, args.steps))}
         line["graph"] = graph_leg(drf, chk, args.steps)
+        line["table_vs_partition"] = table_ab(drf, chk, min(args.steps, 5), lib)
         line["serving"] = serving(drf, [1000, 5000, 20000, 50000])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(items)

@@ -411,13 +411,20 @@ int drf_graph_destroy(drf_graph *g);
  * [256, 8192]; digit_bits: the most index bits of one MSD partition level,
  * 4..10 (a level takes fewer for a short segment);
  * unit_events / item_events: target events per fused unit / per count and
- * emit work item.  Zero fields keep their value; DRF_E_ARG when out of
- * range (nothing changes then). */
+ * emit work item; table_bits: phases above one tile whose protocol indexes
+ * at most 2^table_bits cells (1..24) and that hold at least as many events
+ * as cells are decided by a table of the cells in device memory instead of
+ * emitting records and partitioning them (the sort-free conflict table of
+ * Definition 1: per cell the least tid, the second least and the least
+ * writer); DRF_TABLE_OFF turns this off (the default).  Zero fields keep
+ * their value; DRF_E_ARG when out of range (nothing changes then). */
+#define DRF_TABLE_OFF 255u
 typedef struct {
     uint32_t tile_events;
     uint32_t digit_bits;
     uint32_t unit_events;
     uint32_t item_events;
+    uint32_t table_bits;   /* 0 in drf_ctx_get_tuning: off */
 } drf_tuning;
 
 int drf_ctx_set_tuning(drf_ctx *ctx, const drf_tuning *t);

@@ -43,8 +43,9 @@ using namespace drf;
 
 static_assert(FIXED_SCRATCH_BYTES == DRF_FIXED_SCRATCH_BYTES, "fixed scratch size of the C ABI");
 
-enum KClass { K_COUNT, K_FUSED, K_EMIT, K_HIST, K_SCAN, K_SCATTER, K_TILE, K_SINGLE, K_OTHER, K_NCLASS };
-static const char *KNAMES[K_NCLASS] = {"count", "fused", "emit", "hist", "scan", "scatter", "tile", "single", "other"};
+enum KClass { K_COUNT, K_FUSED, K_EMIT, K_HIST, K_SCAN, K_SCATTER, K_TILE, K_SINGLE, K_TABLE, K_OTHER, K_NCLASS };
+static const char *KNAMES[K_NCLASS] = {"count", "fused", "emit", "hist", "scan", "scatter", "tile", "single", "table",
+                                       "other"};
 
 struct drf_ctx {
     int device = 0;
@@ -68,7 +69,7 @@ struct drf_ctx {
     void *fixed = nullptr;              // the device's fixed scratch array (allocation-free calls)
     bool done_valid = false;
     uint32_t cus = 256;
-    drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 15, 1u << 16};
+    drf_tuning tune = {(uint32_t)drf::TILE, 10, 1u << 15, 1u << 16, 0};
     // per-kernel-class timing
     bool prof = false;
     std::vector<hipEvent_t> ev_free;
@@ -845,6 +846,106 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     }
 }
 
+// Big phases decided by tables (table path): a protocol with at most
+// 2^table_bits cells whose phase holds at least as many events as cells.
+// In waves of up to TABLE_WAVE_WORDS table words: tables cleared, the
+// phases' items evaluated again with every event updating its cell, then
+// the least racy cell of each table offered as a witness candidate.  No
+// record reaches HBM.
+constexpr uint64_t TABLE_WAVE_WORDS = 1ull << 28;   // 1 GiB of tables per wave
+
+bool table_phase(const Call &C, const BigPhase &b, uint64_t cap_words) {
+    const uint32_t tb = C.ctx->tune.table_bits, ib = C.plans[b.proto].index_bits;
+    return tb && ib > 0 && ib <= tb && b.count >= (1ull << ib) && (3ull << ib) <= cap_words;
+}
+
+void run_table_waves(Call &C, const std::vector<BigPhase> &tbig, uint64_t cap_words, Best *best, Cand *cand) {
+    drf_ctx *ctx = C.ctx;
+    hipStream_t st = C.st;
+    void *A = C.A;
+    size_t bi = 0;
+    while (bi < tbig.size()) {
+        // the wave: consecutive table phases within the table budget and
+        // one window of phases
+        uint64_t words = 0;
+        size_t be = bi;
+        while (be < tbig.size()) {
+            const uint64_t w = 3ull << C.plans[tbig[be].proto].index_bits;
+            if (be > bi && (words + w > cap_words || tbig[be].k - tbig[bi].k >= (1ull << 26))) break;
+            words += w;
+            be++;
+        }
+        const uint64_t win_lo = tbig[bi].k, win_n = tbig[be - 1].k - win_lo + 1;
+        std::vector<unsigned long long> tb(win_n, ~0ull);
+        std::vector<TablePhase> tp(be - bi);
+        uint64_t off = 0;
+        for (size_t j = bi; j < be; j++) {
+            const uint32_t cells = 1u << C.plans[tbig[j].proto].index_bits;
+            tb[tbig[j].k - win_lo] = off;
+            tp[j - bi] = TablePhase{off, cells, tbig[j].proto, tbig[j].local, 0};
+            off += 3ull * cells;
+        }
+        std::vector<Item> witems[2];
+        const bool all = bi == 0 && be == tbig.size();
+        if (!all)
+            for (int w = 0; w < 2; w++)
+                for (const Item &it : C.items[w])
+                    if (it.k_lo < win_lo + win_n && it.k_lo + it.span > win_lo) witems[w].push_back(it);
+        Bump b;
+        const size_t o_tab = b.reserve(words * 4);
+        const size_t o_tb = b.reserve(win_n * 8);
+        const size_t o_tp = b.reserve(tp.size() * sizeof(TablePhase));
+        const size_t o_tmin = b.reserve(tp.size() * 4);
+        const size_t o_wi0 = b.reserve(witems[0].size() * sizeof(Item));
+        const size_t o_wi1 = b.reserve(witems[1].size() * sizeof(Item));
+        grow(ctx, ctx->poolB, ctx->sizeB, b.used + ALIGN, st);
+        void *B = ctx->poolB;
+        uint32_t *tabs = at<uint32_t>(B, o_tab);
+        uint32_t *tmin = at<uint32_t>(B, o_tmin);
+        const unsigned long long *dtb = C.put(at<void>(B, o_tb), tb);
+        const TablePhase *dtp = C.put(at<void>(B, o_tp), tp);
+        C.fill_many({{tabs, 0xFFFFFFFFu, words * 4}, {tmin, 0xFFFFFFFFu, tp.size() * 4}});
+        const NestDesc *dnests = at<NestDesc>(A, C.o_nests);
+        const ProtoDesc *dprotos = at<ProtoDesc>(A, C.o_protos);
+        const FixedVal *dfixed = at<FixedVal>(A, C.o_fixed);
+        const uint32_t *dcode = at<uint32_t>(A, C.o_code);
+        const uint32_t *ditemcnt = at<uint32_t>(A, C.o_itemcnt);
+        uint64_t recs = 0;
+        for (size_t j = bi; j < be; j++) recs += tbig[j].count;
+        for (int w = 0; w < 2; w++) {
+            const Item *it = all ? C.ditems[w] : C.put(at<void>(B, w ? o_wi1 : o_wi0), witems[w]);
+            const size_t nit = all ? C.items[w].size() : witems[w].size();
+            unsigned long long *tptr = reinterpret_cast<unsigned long long *>(tabs);
+            for (uint64_t s0 = 0; s0 < nit; s0 += 1u << 30) {
+                const uint32_t n = (uint32_t)std::min<uint64_t>(nit - s0, 1u << 30);
+                const bool wide = w == 1;
+                Prof pr(ctx, st, K_TABLE, w == 0 ? recs : 0, 0);
+                C.dev([=](hipStream_t s) {
+                    return launch_emit(it + s0, n, wide, dnests, dprotos, dfixed, dcode, ditemcnt, dtb, nullptr,
+                                       win_lo, win_n, tptr, 0, s, true);
+                });
+            }
+        }
+        const uint32_t ntp = (uint32_t)tp.size();
+        uint32_t bpt = 1;
+        {
+            const uint64_t per = words / 3 / ntp;   // mean cells per table
+            while (bpt < 64 && (uint64_t)bpt * WG * 16 < per) bpt <<= 1;
+        }
+        {
+            Prof pr(ctx, st, K_TABLE, 0, words * 4);
+            C.dev([=](hipStream_t s) { return launch_table_scan(dtp, ntp, tabs, tmin, bpt, s); });
+            C.dev([=](hipStream_t s) { return launch_table_offer(dtp, ntp, tabs, tmin, cand, best, s); });
+        }
+        {
+            Prof pr(ctx, st, K_OTHER, 0, 0);
+            C.dev([=](hipStream_t s) { return launch_pick(cand, ntp, best, s); });
+        }
+        C.tr.mark("table wave", be - bi);
+        bi = be;
+    }
+}
+
 // Fused units in launch order: largest first by the power of two of their
 // work, input order within one power (a counting sort, linear in the units).
 std::vector<Unit> order_units(const std::vector<Unit> &units, const std::vector<uint64_t> &work) {
@@ -1120,7 +1221,18 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             C.tr.mark("fused launched", units[0].size() + units[1].size());
         }
 
-        // ---- big phases, in waves under the scratch budget
+        // ---- big phases decided by tables (when enabled), then the rest in
+        // waves under the scratch budget
+        // (not in allocation-free or recorded calls: their pool B is fixed
+        // once for the call)
+        if (ctx->tune.table_bits && !noalloc && !rec && !big.empty()) {
+            const uint64_t cap_words =
+                std::min<uint64_t>(TABLE_WAVE_WORDS, (ctx->limit > ctx->sizeA ? ctx->limit - ctx->sizeA : 0) / 8);
+            std::vector<BigPhase> tbig, rest;
+            for (const BigPhase &bp : big) (table_phase(C, bp, cap_words) ? tbig : rest).push_back(bp);
+            big.swap(rest);
+            if (!tbig.empty()) run_table_waves(C, tbig, cap_words, best, cand);
+        }
         if (!big.empty()) {
             const uint64_t a_end = (C.needA + ALIGN - 1) & ~(ALIGN - 1);
             uint64_t budget = noalloc ? (FIXED_SCRATCH_BYTES > a_end ? FIXED_SCRATCH_BYTES - a_end : 0)
@@ -1461,6 +1573,11 @@ int drf_ctx_set_tuning(drf_ctx *ctx, const drf_tuning *t) {
     if (t->item_events) {
         if (t->item_events < 256) return DRF_E_ARG;
         n.item_events = t->item_events;
+    }
+    if (t->table_bits) {
+        if (t->table_bits == DRF_TABLE_OFF) n.table_bits = 0;
+        else if (t->table_bits > 24) return DRF_E_ARG;
+        else n.table_bits = t->table_bits;
     }
     ctx->tune = n;
     return DRF_OK;

@@ -450,6 +450,27 @@ struct EmitSink {
     }
 };
 
+// Table path of a big phase: each access event updates its cell of the
+// phase's table in device memory (least tid, second least tid, least
+// writing tid; three arrays of 2^index_bits words at `tab`), with the same
+// one-pass rule as the LDS aggregation: atomicMin on the least tid returns
+// the minimum before it, and the larger of two different tids is offered to
+// the second least.
+DEV void table_update(uint32_t *tab, uint32_t cells, uint32_t idx, uint32_t tid, bool wr) {
+    const uint32_t old = atomicMin(tab + idx, tid);
+    if (old != NONE32 && old != tid) atomicMin(tab + cells + idx, old > tid ? old : tid);
+    if (wr) atomicMin(tab + 2 * cells + idx, tid);
+}
+
+struct TableSink {
+    uint32_t *tab;              // the current phase's table
+    uint32_t cells;
+    uint32_t tid;
+    DEV void acc(bool act, uint32_t idx, uint32_t mode) {
+        if (act) table_update(tab, cells, idx, tid, (mode & 1u) != 0);
+    }
+};
+
 // Compiled leaf: per chunk of iterations the workgroup first evaluates the
 // uniform slots (slot-major, iterations padded to whole waves so every wave
 // runs one slot program), the phase and the thread limit of each iteration
@@ -548,7 +569,9 @@ struct CalLds {
     uint32_t uoff[CAL_MAXU + 1];
 };
 
-template <typename T>
+// TABLE: lds_base holds each phase's table offset (in words from recs as
+// uint32_t*) instead of its record position; events update the tables.
+template <typename T, bool TABLE>
 DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const FixedVal *__restrict__ fixed,
                   const uint32_t *__restrict__ code, const unsigned long long *lds_base, uint32_t *lds_cur,
                   unsigned long long *__restrict__ recs, unsigned long long cap, CalLds &L) {
@@ -621,6 +644,10 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
                     const uint64_t m = ballot(act[q]);
                     if (m == 0) continue;
                     go[q] = true;
+                    if constexpr (TABLE) {
+                        p0[q] = b;
+                        continue;
+                    }
                     na[q] = (uint32_t)__builtin_popcountll(m);
                     uint32_t r0 = 0;
                     if (lane_id() == 0) r0 = atomicAdd(&lds_cur[pi], na[q] * nacc);
@@ -637,6 +664,12 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
                     for (uint32_t q = 0; q < EB; q++) {
                         if (!go[q]) continue;
                         const uint32_t v = cal_eval(h, tid, L.u + i0 + q, chp);
+                        if constexpr (TABLE) {
+                            if (act[q])   // a table phase: its protocol's index bits are at most 31
+                                table_update(reinterpret_cast<uint32_t *>(recs) + p0[q], 1u << (pd.ib & 31u), v,
+                                             tid, (h.mode & 1u) != 0);
+                            continue;
+                        }
                         const unsigned long long pos = p0[q] + (unsigned long long)j * na[q];
                         if (act[q] && pos < cap)
                             recs[pos] = ((unsigned long long)v << 32) | ((unsigned long long)tid << 1) | h.mode;
@@ -649,7 +682,7 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
     }
 }
 
-template <typename T, bool WIDE>
+template <typename T, bool WIDE, bool TABLE>
 __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, const NestDesc *__restrict__ nests,
                                               const ProtoDesc *__restrict__ protos,
                                               const FixedVal *__restrict__ fixed, const uint32_t *__restrict__ code,
@@ -671,7 +704,8 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
         unsigned long long v = ~0ull;
         if (c && k >= win_lo && k - win_lo < win_n) {
             const unsigned long long b = big_base[k - win_lo];
-            if (b != ~0ull) v = b + atomicAdd(&cursor[k - win_lo], (unsigned long long)c);
+            if constexpr (TABLE) v = b;   // the phase's table (or none)
+            else if (b != ~0ull) v = b + atomicAdd(&cursor[k - win_lo], (unsigned long long)c);
         }
         lds_base[i] = v;
         lds_cur[i] = 0;
@@ -679,7 +713,7 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
     __syncthreads();
     if constexpr (!WIDE) {
         if (nd.cal_off != NONE32) {
-            emit_cal<T>(it, nd, pd, fixed, code, lds_base, lds_cur, recs, cap, lds_cal);
+            emit_cal<T, TABLE>(it, nd, pd, fixed, code, lds_base, lds_cur, recs, cap, lds_cal);
             return;
         }
     }
@@ -696,13 +730,20 @@ __global__ __launch_bounds__(WG) void k_emit(const Item *__restrict__ items, con
         const uint32_t *leaf = code + nd.code_off;
         bool ovf = false;
         EmitSink sink{nullptr, 0, recs, cap, tid};
+        TableSink tsink{nullptr, 0, tid};
         for (uint64_t f = it.f0; f < it.f1; f++) {
             const uint32_t i = (uint32_t)(odo.phase - it.k_lo);
             const unsigned long long b = lds_base[i];
             if (b != ~0ull && tid0 < tid_limit<T>(nd, code, vars, pd.n)) {
-                sink.cur = &lds_cur[i];
-                sink.base = b;
-                run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+                if constexpr (TABLE) {
+                    tsink.tab = reinterpret_cast<uint32_t *>(recs) + b;
+                    tsink.cells = 1u << (pd.ib & 31u);
+                    run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, tsink);
+                } else {
+                    sink.cur = &lds_cur[i];
+                    sink.base = b;
+                    run_leaf<T, WIDE>(leaf, vars, (T)tid, act0, ovf, sink);
+                }
             }
             odo.next(nd, vars);
         }
@@ -2308,6 +2349,42 @@ __global__ void k_pick(const Cand *__restrict__ cands, uint64_t n, const uint32_
 }
 
 // ================================================================ results
+// Least racy cell of each table phase (a second tid and a writer): blocks
+// of a table scan strided slices of its cells; each thread's first racy
+// cell is the least of its slice, and the minimum reaches tmin by
+// atomicMin.
+__global__ void k_table_scan(const TablePhase *__restrict__ tp, const uint32_t *__restrict__ tabs,
+                             uint32_t *__restrict__ tmin) {
+    const TablePhase t = tp[blockIdx.y];
+    const uint32_t *t1 = tabs + t.off + t.cells, *w0 = t1 + t.cells;
+    uint32_t first = NONE32;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < t.cells; c += gridDim.x * blockDim.x)
+        if (t1[c] != NONE32 && w0[c] != NONE32) {
+            first = c;
+            break;
+        }
+    first = wave_min(first);
+    if (lane_id() == 0 && first != NONE32) atomicMin(&tmin[blockIdx.y], first);
+}
+
+// The witness candidate of each table phase: its least racy cell with the
+// pair (t0, t1) if t0 writes, else (t0, w0).
+__global__ void k_table_offer(const TablePhase *__restrict__ tp, uint32_t ntp, const uint32_t *__restrict__ tabs,
+                              const uint32_t *__restrict__ tmin, Cand *__restrict__ cands, Best *__restrict__ best) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntp) return;
+    const TablePhase t = tp[j];
+    Cand *my = &cands[j];
+    my->key = ~0ull;
+    my->pair = 0;
+    my->proto = t.proto;
+    const uint32_t c = tmin[j];
+    if (c == NONE32) return;
+    const uint32_t *t0 = tabs + t.off;
+    const uint32_t a = t0[c], b = t0[t.cells + c], w = t0[2 * t.cells + c];
+    offer(best, my, t.proto, t.phase, c, a, w == a ? b : w);
+}
+
 __global__ void k_result(uint32_t count, const uint32_t *__restrict__ count_dev, const ResultIn *__restrict__ rin,
                          const Best *__restrict__ best, const unsigned long long *__restrict__ nrec,
                          const uint32_t *__restrict__ ovf_flags, drf_result_dev *__restrict__ out) {
@@ -2389,12 +2466,31 @@ hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const Nest
                        const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
                        const uint32_t *item_cnt, const unsigned long long *big_base,
                        unsigned long long *cursor, uint64_t win_lo, uint64_t win_n, unsigned long long *recs,
-                       unsigned long long cap, hipStream_t s) {
-    if (wide)
-        return launch(k_emit<uint64_t, true>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                       unsigned long long cap, hipStream_t s, bool table) {
+    if (table) {
+        if (wide)
+            return launch(k_emit<uint64_t, true, true>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                          item_cnt, big_base, cursor, win_lo, win_n, recs, cap);
+        return launch(k_emit<uint32_t, false, true>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
                       item_cnt, big_base, cursor, win_lo, win_n, recs, cap);
-    return launch(k_emit<uint32_t, false>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code, item_cnt,
-                  big_base, cursor, win_lo, win_n, recs, cap);
+    }
+    if (wide)
+        return launch(k_emit<uint64_t, true, false>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                      item_cnt, big_base, cursor, win_lo, win_n, recs, cap);
+    return launch(k_emit<uint32_t, false, false>, dim3(nitems), dim3(WG), s, items, nests, protos, fixed, code,
+                  item_cnt, big_base, cursor, win_lo, win_n, recs, cap);
+}
+
+hipError_t launch_table_scan(const TablePhase *tp, uint32_t ntp, const uint32_t *tabs, uint32_t *tmin,
+                             uint32_t blocks_per_table, hipStream_t s) {
+    if (ntp == 0) return hipSuccess;
+    return launch(k_table_scan, dim3(blocks_per_table, ntp), dim3(WG), s, tp, tabs, tmin);
+}
+
+hipError_t launch_table_offer(const TablePhase *tp, uint32_t ntp, const uint32_t *tabs, const uint32_t *tmin,
+                              Cand *cands, Best *best, hipStream_t s) {
+    if (ntp == 0) return hipSuccess;
+    return launch(k_table_offer, dim3((ntp + 255) / 256), dim3(256), s, tp, ntp, tabs, tmin, cands, best);
 }
 
 hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, bool wide, const NestDesc *nests,

@@ -69,7 +69,22 @@ hipError_t launch_emit(const Item *items, uint32_t nitems, bool wide, const Nest
                        const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,
                        const uint32_t *item_cnt, const unsigned long long *big_base,
                        unsigned long long *cursor, uint64_t win_lo, uint64_t win_n, unsigned long long *recs,
-                       unsigned long long cap, hipStream_t s);
+                       unsigned long long cap, hipStream_t s, bool table = false);
+
+// A big phase decided by its table (table path): offset of its three cell
+// arrays in the table region (in 32-bit words), its cell count (a power of
+// two), its protocol and local phase.
+struct TablePhase {
+    uint64_t off;
+    uint32_t cells;
+    uint32_t proto;
+    uint32_t phase;
+    uint32_t pad;
+};
+hipError_t launch_table_scan(const TablePhase *tp, uint32_t ntp, const uint32_t *tabs, uint32_t *tmin,
+                             uint32_t blocks_per_table, hipStream_t s);
+hipError_t launch_table_offer(const TablePhase *tp, uint32_t ntp, const uint32_t *tabs, const uint32_t *tmin,
+                              Cand *cands, Best *best, hipStream_t s);
 
 hipError_t launch_fused(const Unit *units, uint32_t nunits, uint32_t *qhead, bool wide, const NestDesc *nests,
                         const ProtoDesc *protos, const FixedVal *fixed, const uint32_t *code,

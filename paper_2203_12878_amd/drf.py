@@ -44,9 +44,13 @@ class GraphCaps(ctypes.Structure):
                 ("max_phases", ctypes.c_uint64), ("max_units", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+TABLE_OFF = 255
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_events", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32),
-                ("unit_events", ctypes.c_uint32), ("item_events", ctypes.c_uint32)]
+                ("unit_events", ctypes.c_uint32), ("item_events", ctypes.c_uint32),
+                ("table_bits", ctypes.c_uint32)]
 
 
 class _Result(ctypes.Structure):
@@ -428,8 +432,9 @@ class Checker:
         if rc != OK:
             raise DrfError(rc, "drf_ctx_release")
 
-    def set_tuning(self, tile_events=0, digit_bits=0, unit_events=0, item_events=0):
-        t = Tuning(tile_events, digit_bits, unit_events, item_events)
+    def set_tuning(self, tile_events=0, digit_bits=0, unit_events=0, item_events=0, table_bits=0):
+        """Zero keeps a field; table_bits=TABLE_OFF turns the table path off."""
+        t = Tuning(tile_events, digit_bits, unit_events, item_events, table_bits)
         rc = lib().drf_ctx_set_tuning(self._ctx, ctypes.byref(t))
         if rc != OK:
             raise DrfError(rc, "drf_ctx_set_tuning")

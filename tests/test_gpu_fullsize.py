@@ -6,7 +6,8 @@ oracle), on the full synthetic workloads:
   cells) for seeds whose protocol writes, through the plain and the
   batched path;
 * the whole mixed batch (4096 protocols) and the whole tree-reduction
-  batch (2048 instances) in one batched check each;
+  batch (2048 instances) in one batched check each, with the big phases
+  partitioned and (a second time) with the dense ones decided by tables;
 * a served Poisson stream at 5k req/s (1000 requests drawn 70/30 from the
   mixed and tree generators), every request against its stored result.
 
@@ -72,19 +73,29 @@ def test_large_protocol_with_writes(chk, seed):
     assert _mismatches(batched, exp) == []
 
 
-def test_mixed_batch_full(chk):
+@pytest.mark.parametrize("table_bits", [255, 20])
+def test_mixed_batch_full(chk, table_bits):
     items = [(t, n) for t, n, _ in w.gen_mixed_batch(0, 4096)]
     exp = _expected("mixed")
-    got = chk.check_batch(items)
+    chk.set_tuning(table_bits=table_bits)   # 255: partition path only; 20: dense big phases by tables
+    try:
+        got = chk.check_batch(items)
+    finally:
+        chk.set_tuning(table_bits=255)
     bad = _mismatches(got, exp)
     assert not bad, "%d of %d differ, first %r" % (len(bad), len(items), bad[:2])
     assert sum(g.racy for g in got) == sum(e["racy"] for e in exp) > 0
 
 
-def test_tree_batch_full(chk):
+@pytest.mark.parametrize("table_bits", [255, 24])
+def test_tree_batch_full(chk, table_bits):
     items = [(t, n) for t, n, _ in w.gen_tree_batch(0, 2048)]
     exp = _expected("tree")
-    got = chk.check_batch(items)
+    chk.set_tuning(table_bits=table_bits)
+    try:
+        got = chk.check_batch(items)
+    finally:
+        chk.set_tuning(table_bits=255)
     bad = _mismatches(got, exp)
     assert not bad, "%d of %d differ, first %r" % (len(bad), len(items), bad[:2])
 

@@ -157,3 +157,32 @@ def test_multi_block_items(chk):
     got = chk.check_batch(items)
     _same(got, o2.check_many(items, jobs=4), items)
     assert [g.racy for g in got] == [1, 0, 0]
+
+
+def test_table_path_on_dense_big_phases():
+    """Big phases decided by cell tables (table_bits on) against the C
+    oracle: dense phases with races at the first, a middle and the last
+    cell, read-only sharing, same-thread repeats, writers only, several
+    table phases per protocol and several protocols per wave, and a
+    protocol too sparse for a table next to them."""
+    from paper_2203_12878_amd import drf
+    items = [
+        ("(wr (mod tid 4096))", 65536),                                   # every cell written by 16 threads
+        ("(seq (rd (mod tid 8192)) (if (= tid 40000) (wr 5000) (skip)))", 65536),   # one writer in a read phase
+        ("(seq (rd (mod tid 8192)) (if (= tid 8191) (wr 8191) (skip)))", 16384),    # race at the last cell
+        ("(seq (rd (mod tid 2048)) (sync) (wr (mod (* tid 3) 2048)))", 20000),
+        ("(foru x 0 4 (wr (+ (* (/ tid 4) 4) x)))", 65536),                # four threads write the same four cells
+        ("(fors x 0 3 (seq (wr (mod (+ tid x) 4096)) (sync)))", 4096),    # own cells, DRF, three table phases
+        ("(fors x 0 3 (seq (wr (mod (+ tid x) 4096)) (rd (mod (+ tid 1) 4096)) (sync)))", 4096),   # racy
+        ("(rd (mod tid 1024))", 50000),                                   # read-only sharing: DRF
+        ("(wr (* tid 97))", 30000),                                       # sparse: partitioned
+    ]
+    want = o2.check_many(items, jobs=8)
+    chk = drf.Checker(0)
+    for bits in (255, 24, 12):
+        chk.set_tuning(table_bits=bits)
+        got = chk.check_batch(items)
+        for it, g, e in zip(items, got, want):
+            assert g.key() == e.key(), (bits, it, g, e)
+    chk.close()
+    assert sum(e.racy for e in want) >= 4
