@@ -1659,27 +1659,40 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, const uint3
                 }
             }
             __syncthreads();
-            for (uint32_t ni = 0; ni < ncache; ni++) {
-                const uint32_t sb = lds_st.base[ni];
-                if (sb == NONE32) continue;
-                const NestDesc &nd = nests[pd.nest0 + ni];
-                const uint32_t cs = lds_st.cnt[ni];
-                const uint32_t *cal = code + nd.cal_off;
-                const uint32_t nuni = rfl(cal[1]);
-                for (uint32_t fi = threadIdx.x; fi < cs; fi += WG) {
-                    T vars[MAXSLOTS];
-                    for (int z = 0; z < MAXSLOTS; z++) vars[z] = 0;
-                    load_fixed<T>(nd, fixed, vars);
-                    Odo<T> odo;
-                    odo.start(nd, lds_st.f0[ni] + fi, vars);
-                    lds_st.w[sb + fi] = (uint32_t)(odo.phase - u.k0);
-                    lds_st.w[sb + cs + fi] = tid_limit<T>(nd, code, vars, pd.n);
+            // staging in blocks of (nest, value): the phase and thread limit,
+            // then each uniform slot, for all of the nest's staged iterations
+            // (a lane per iteration); the waves take the blocks in turn, so a
+            // block's program is the same on all lanes of its wave
+            {
+                const uint32_t wv = threadIdx.x >> 6;
+                uint32_t blk = 0;
+                for (uint32_t ni = 0; ni < ncache; ni++) {
+                    const uint32_t sb = lds_st.base[ni];
+                    if (sb == NONE32) continue;
+                    const NestDesc &nd = nests[pd.nest0 + ni];
+                    const uint32_t cs = lds_st.cnt[ni];
+                    const uint32_t *cal = code + nd.cal_off;
+                    const uint32_t nuni = rfl(cal[1]);
                     const uint32_t *up = cal + 3;
-                    for (uint32_t z = 0; z < nuni; z++) {
-                        bool o = false;
-                        const uint32_t len = rfl(up[0]);
-                        lds_st.w[sb + (2 + z) * cs + fi] = (uint32_t)eval_expr<T, false>(up + 1, len, vars, (T)0, o);
-                        up += 1 + len;
+                    for (uint32_t z = 0; z <= nuni; z++) {   // z = 0: phase and limit; z > 0: slot z - 1
+                        const uint32_t *prog = up;
+                        if (z > 0) up += 1 + rfl(up[0]);
+                        if ((blk++ & (WG / 64 - 1)) != wv) continue;
+                        for (uint32_t fi = lane_id(); fi < cs; fi += 64) {
+                            T vars[MAXSLOTS];
+                            for (int y = 0; y < MAXSLOTS; y++) vars[y] = 0;
+                            load_fixed<T>(nd, fixed, vars);
+                            Odo<T> odo;
+                            odo.start(nd, lds_st.f0[ni] + fi, vars);
+                            if (z == 0) {
+                                lds_st.w[sb + fi] = (uint32_t)(odo.phase - u.k0);
+                                lds_st.w[sb + cs + fi] = tid_limit<T>(nd, code, vars, pd.n);
+                            } else {
+                                bool o = false;
+                                lds_st.w[sb + (1 + z) * cs + fi] =
+                                    (uint32_t)eval_expr<T, false>(prog + 1, rfl(prog[0]), vars, (T)0, o);
+                            }
+                        }
                     }
                 }
             }
