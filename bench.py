@@ -44,15 +44,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# LDS: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
-LDS_PEAK_GBS = 128 * 256 * 2.4
+# 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # bytes per record the method must move with records materialized in HBM
 # (one 8-byte record write, its read-back by the conflict pass, and the
 # 8-byte histogram read of one partition level)
 EFFECTIVE_BYTES_PER_RECORD = 24
-# the fused path writes each 8-byte record into LDS once and reads it back
-# once before deciding it
-FUSED_LDS_BYTES_PER_RECORD = 16
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -103,10 +100,10 @@ def kernels_sha256() -> str:
     return h.hexdigest()
 
 
-def committed_traffic(kernel: str, wl: str):
-    """HBM bytes per launch of `kernel` on workload `wl` from the committed
-    rocprofv3 counter summary, or None when none exists or the kernels have
-    changed since the counters were taken."""
+def committed_value(kernel: str, wl: str, key: str = "traffic_bytes_per_launch"):
+    """A per-launch value of `kernel` on workload `wl` from the committed
+    rocprofv3 counter summary (HBM bytes, VALU lane operations), or None when
+    none exists or the kernels have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, wl))
     if not os.path.exists(path):
         return None
@@ -119,7 +116,7 @@ def committed_traffic(kernel: str, wl: str):
     if vals.get("kernels_sha256") != kernels_sha256():
         return None
     try:
-        return int(vals["traffic_bytes_per_launch"])
+        return int(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -252,18 +249,21 @@ def roofline(stats, steps, records, wl):
     launches = max(1, d["launches"])
     avg_ms = d["ms"] / launches
     if dname == "fused":
-        # the fused path keeps records in LDS: its records are those not
-        # emitted to HBM; bound against the LDS bandwidth
-        emitted = stats.get("emit", {}).get("records", 0) // max(1, steps)
-        recs = (records - emitted) * steps
-        achieved = recs * FUSED_LDS_BYTES_PER_RECORD / (d["ms"] / 1e3) / 1e9
-        return {"kernel": dname, "bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
-                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
-                "traffic": committed_traffic(dname, wl), "records_per_launch": recs // launches,
-                "lds_bytes_per_record": FUSED_LDS_BYTES_PER_RECORD, "avg_launch_ms": round(avg_ms, 4)}
+        # the fused path keeps its records in LDS and moves almost nothing
+        # through HBM: it is bounded by instruction issue.  achieved = VALU
+        # lane operations per launch (the committed rocprofv3 SQ_INSTS_VALU
+        # x 64 of this workload, null once the kernels change) over the
+        # launch time measured now, against the chip's 32-bit VALU peak
+        ops = committed_value(dname, wl, "valu_lane_ops_per_launch")
+        achieved = ops / (avg_ms / 1e3) / 1e9 if ops else None
+        return {"kernel": dname, "bound": "alu", "achieved": round(achieved, 1) if achieved else None,
+                "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gops/s",
+                "frac": round(achieved / VALU_PEAK_GOPS, 4) if achieved else None,
+                "traffic": committed_value(dname, wl), "valu_lane_ops_per_launch": ops,
+                "avg_launch_ms": round(avg_ms, 4)}
     achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9
     return {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(dname, wl),
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_value(dname, wl),
             "bytes_per_launch": d["bytes"] // launches, "avg_launch_ms": round(avg_ms, 4)}
 
 
