@@ -1919,7 +1919,34 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, const uint3
                             const uint32_t *hp = lds_st.w + lds_st.act_hofs[a] + j * HSTRIDE;
                             const uint32_t mode = hp[0];
                             const uint32_t t1 = tid + (pend - p < L - tid ? pend - p : L - tid);
-                            if (hp[1] == 1u) {
+                            if (hp[1] == 1u && hp[3] != CAL_K_AND && hp[7] != CAL_K_AND) {
+                                // fixed form v = ((tid + c0) m0-op m0) * a + U, then pk-op pa,
+                                // advanced tid by tid: x = (tid + c0) mod m0 steps by one
+                                // (back to 0 at m0), v by a (mod pa: one conditional
+                                // subtraction of pa); every value stays below 2^32 (32-bit plan)
+                                const uint32_t c0 = hp[2], m0k = hp[3], m0 = hp[4], am = hp[5], us = hp[6];
+                                const uint32_t pk = hp[7], pa = hp[8], m0mag = hp[9], m0sh = hp[10];
+                                const uint32_t pamag = hp[11], pash = hp[12];
+                                const uint32_t uv = us != NONE32 ? U[us * cs] : 0u;
+                                const bool pmod = pk == CAL_K_MOD, xmod = m0k == CAL_K_MOD;
+                                const uint32_t astep = pmod ? fixed_op(am, CAL_K_MOD, pa, pamag, pash) : am;
+                                const uint32_t v0 = fixed_op(uv, pk, pa, pamag, pash);   // v at x = 0
+                                uint32_t x = fixed_op(tid + c0, m0k, m0, m0mag, m0sh);
+                                uint32_t v = fixed_op(x * am + uv, pk, pa, pamag, pash);
+                                for (; tid < t1; tid++, p++) {
+                                    lds_rec[ph(p)] = pre | ((unsigned long long)v << ish) |
+                                                     ((unsigned long long)tid << 1) | mode;
+                                    x++;
+                                    if (xmod && x == m0) {
+                                        x = 0;
+                                        v = v0;
+                                    } else if (pmod) {
+                                        v = v >= pa - astep ? v - (pa - astep) : v + astep;
+                                    } else {
+                                        v += astep;
+                                    }
+                                }
+                            } else if (hp[1] == 1u) {
                                 const uint32_t c0 = hp[2], m0k = hp[3], m0 = hp[4], am = hp[5], us = hp[6];
                                 const uint32_t pk = hp[7], pa = hp[8], m0mag = hp[9], m0sh = hp[10];
                                 const uint32_t pamag = hp[11], pash = hp[12];

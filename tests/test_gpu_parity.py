@@ -176,6 +176,9 @@ def test_table_path_on_dense_big_phases():
         ("(fors x 0 3 (seq (wr (mod (+ tid x) 4096)) (rd (mod (+ tid 1) 4096)) (sync)))", 4096),   # racy
         ("(rd (mod tid 1024))", 50000),                                   # read-only sharing: DRF
         ("(wr (* tid 97))", 30000),                                       # sparse: partitioned
+        # values beyond 2^32 (the 64-bit evaluator) in dense phases
+        ("(wr (mod (* tid 4294967311) 4096))", 65536),
+        ("(seq (rd (mod (* tid 8589934597) 2048)) (if (= tid 7) (wr 5) (skip)))", 8192),
     ]
     want = o2.check_many(items, jobs=8)
     chk = drf.Checker(0)
