@@ -1184,7 +1184,8 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
     while ((1u << hb) < 2 * nc && (2u << hb) <= max_slots) hb++;
     const uint32_t S = 1u << hb, cap = S - S / 4;
     uint32_t *K = mem, *T0 = K + S, *W0 = T0 + S, *T1 = W0 + S;
-    for (uint32_t k = threadIdx.x; k < 4 * S; k += NT) K[k] = NONE32;
+    uint4 *K4 = reinterpret_cast<uint4 *>(K);   // mem is 16-byte aligned: cleared 16 bytes at a time
+    for (uint32_t k = threadIdx.x; k < S; k += NT) K4[k] = make_uint4(NONE32, NONE32, NONE32, NONE32);
     if (threadIdx.x == 0) {
         red[RED_CAND] = 0;
         red[RED_OVF] = 0;
