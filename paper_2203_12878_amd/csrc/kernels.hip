@@ -1105,8 +1105,11 @@ DEV void block_minmax64(unsigned long long &lo, unsigned long long &hi, uint32_t
 //          access cannot race).  When no cell repeats the group is race
 //          free; otherwise the records left are aggregated per cell as in
 //          the table method, in an LDS hash table.
-//  sort    when the survivors hold more distinct cells than the hash table
-//          takes: they are sorted and scanned.
+//  split   (SPLIT) when the survivors hold more distinct cells than the
+//          hash table takes, a second hash of the cell splits them four
+//          ways and each part takes a table pass of its own.
+//  sort    when a table still overflows (or without SPLIT): the survivors
+//          are sorted and scanned.
 // Tiles run 512-thread workgroups: at most 16 records per thread stay in
 // registers, and the two workgroups the LDS admits per CU give 4 waves per
 // SIMD.
@@ -1153,6 +1156,7 @@ struct Scratch {
     static_assert(surv_words <= fwords, "compact survivors overlap the repeated bitmap");
     static_assert((words - surv_words) / 4 >= 2 * surv_cap, "no room for the table above the survivors");
     static_assert(hslots * 4 <= words, "hash table exceeds the scratch");
+    static_assert(2 * fwords + 64 <= words, "no words above the filter bitmaps");
 };
 
 // One record's update of its cell's aggregate (least tid t0, least tid
@@ -1175,9 +1179,12 @@ DEV void cell_update(uint32_t *t0, uint32_t *t1, uint32_t *w0, uint32_t tid, boo
 // twice the survivors.  Probing never takes more steps than there are
 // slots; more distinct cells than three quarters of the slots is an
 // overflow.  src(f) calls f(record) for each survivor this thread owns (the
-// same ones on every call).  Returns 1 (racy cell found), 0 (none) or -1
-// (overflow: the caller sorts instead).
-template <int NT, class Src>
+// same ones on every call); with B4 it calls f(r, vm) for them four at a
+// time (r[d] is one when bit d of vm is set), and the four records' atomics
+// are in flight together (more registers: the fused path, at its register
+// budget, takes records one by one).  Returns 1 (racy cell found), 0 (none)
+// or -1 (overflow: the caller falls back to another method).
+template <int NT, bool B4, class Src>
 DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsigned long long lo, uint32_t *mem,
                  uint32_t max_slots, uint32_t *red, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     uint32_t hb = 8;
@@ -1192,36 +1199,107 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
     }
     __syncthreads();
     bool ovf = false;
-    src([&](unsigned long long r) {
-        const uint32_t c = (uint32_t)((r >> ish) - lo);
-        const uint32_t tid = (uint32_t)(r >> 1) & tmask;
-        uint32_t h = (c * 0x9E3779B1u) >> (32 - hb);
-        bool placed = false;
-        for (uint32_t st = 0; st < S; st++) {
-            const uint32_t old = atomicCAS(&K[h], NONE32, c);
-            if (old == NONE32 || old == c) {
-                if (old == NONE32 && atomicAdd(&red[RED_CAND], 1u) >= cap) ovf = true;
-                placed = true;
-                break;
+    if constexpr (B4) {
+        src([&](const unsigned long long (&r)[4], uint32_t vm) {
+            uint32_t c[4], h[4], o[4];
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                c[d] = (uint32_t)((r[d] >> ish) - lo);
+                h[d] = (c[d] * 0x9E3779B1u) >> (32 - hb);
+                o[d] = NONE32;
+                if ((vm >> d) & 1u) o[d] = atomicCAS(&K[h[d]], NONE32, c[d]);
             }
-            h = (h + 1) & (S - 1);
-        }
-        if (placed) {
-            cell_update(T0 + h, T1 + h, W0 + h, tid, (r & 1ull) != 0);
-        } else {
-            ovf = true;
-        }
-    });
+            // a slot taken by another cell: probe on, one record at a time
+            uint32_t placed = 0, fresh = 0;
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                if (!((vm >> d) & 1u)) continue;
+                uint32_t old = o[d];
+                for (uint32_t st = 1; st < S && old != NONE32 && old != c[d]; st++) {
+                    h[d] = (h[d] + 1) & (S - 1);
+                    old = atomicCAS(&K[h[d]], NONE32, c[d]);
+                }
+                if (old == NONE32 || old == c[d]) {
+                    placed |= 1u << d;
+                    fresh += old == NONE32 ? 1u : 0u;
+                } else {
+                    ovf = true;
+                }
+            }
+            // new cells of the wave counted by one atomic of its first active lane
+            const uint64_t b0 = ballot(fresh & 1u), b1 = ballot(fresh & 2u), b2 = ballot(fresh & 4u);
+            const uint32_t nf = (uint32_t)(__builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
+                                           4 * __builtin_popcountll(b2));
+            if (nf) {
+                const uint32_t leader = (uint32_t)__builtin_ctzll(ballot(true));
+                uint32_t base = 0;
+                if (lane_id() == leader) base = atomicAdd(&red[RED_CAND], nf);
+                base = readlane(base, leader);
+                if (base + nf > cap) ovf = true;
+            }
+            // the cells' aggregates (cell_update, four records at a time)
+            uint32_t t0o[4], tid[4];
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                tid[d] = (uint32_t)(r[d] >> 1) & tmask;
+                t0o[d] = NONE32;
+                if ((placed >> d) & 1u) {
+                    t0o[d] = atomicMin(T0 + h[d], tid[d]);
+                    if (r[d] & 1ull) atomicMin(W0 + h[d], tid[d]);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 4; d++)
+                if (((placed >> d) & 1u) && t0o[d] != NONE32 && t0o[d] != tid[d])
+                    atomicMin(T1 + h[d], t0o[d] > tid[d] ? t0o[d] : tid[d]);
+        });
+    } else {
+        src([&](unsigned long long r) {
+            const uint32_t c = (uint32_t)((r >> ish) - lo);
+            const uint32_t tid = (uint32_t)(r >> 1) & tmask;
+            uint32_t h = (c * 0x9E3779B1u) >> (32 - hb);
+            bool placed = false;
+            for (uint32_t st = 0; st < S; st++) {
+                const uint32_t old = atomicCAS(&K[h], NONE32, c);
+                if (old == NONE32 || old == c) {
+                    if (old == NONE32 && atomicAdd(&red[RED_CAND], 1u) >= cap) ovf = true;
+                    placed = true;
+                    break;
+                }
+                h = (h + 1) & (S - 1);
+            }
+            if (placed) {
+                cell_update(T0 + h, T1 + h, W0 + h, tid, (r & 1ull) != 0);
+            } else {
+                ovf = true;
+            }
+        });
+    }
     if (ovf) red[RED_OVF] = 1;
     __syncthreads();
     if (red[RED_OVF]) return -1;
     // least racy cell, with its slot in the low bits (a cell has one slot)
     unsigned long long best = ~0ull, none = 0;
-    for (uint32_t k = threadIdx.x; k < S; k += NT)
-        if (K[k] != NONE32 && T1[k] != NONE32 && W0[k] != NONE32) {
-            const unsigned long long c = ((unsigned long long)K[k] << 32) | k;
-            best = c < best ? c : best;
+    if constexpr (B4) {
+        // four slots a thread per step
+        const uint4 *T14 = reinterpret_cast<const uint4 *>(T1), *W04 = reinterpret_cast<const uint4 *>(W0);
+        for (uint32_t q = threadIdx.x; q < S / 4; q += NT) {
+            const uint4 kv = K4[q], tv = T14[q], wv = W04[q];
+            const uint32_t kk[4] = {kv.x, kv.y, kv.z, kv.w}, tt[4] = {tv.x, tv.y, tv.z, tv.w},
+                           ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                const unsigned long long c = ((unsigned long long)kk[d] << 32) | (4 * q + (uint32_t)d);
+                if ((kk[d] != NONE32) & (tt[d] != NONE32) & (ww[d] != NONE32)) best = c < best ? c : best;
+            }
         }
+    } else {
+        for (uint32_t k = threadIdx.x; k < S; k += NT)
+            if (K[k] != NONE32 && T1[k] != NONE32 && W0[k] != NONE32) {
+                const unsigned long long c = ((unsigned long long)K[k] << 32) | k;
+                best = c < best ? c : best;
+            }
+    }
     block_minmax64(best, none, red);
     if (best == ~0ull) return 0;
     const uint32_t k = (uint32_t)best;
@@ -1235,7 +1313,7 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
 // Bit of a cell in the filter bitmaps: its offset from the least cell when
 // the span fits the bitmap, else a multiplicative hash of the cell.  Equal
 // cells always share a bit, so no cell touched twice can be missed; a hash
-// collision only lets a single record through to the exact sort.
+// collision only lets a single record through to the exact aggregation.
 DEV uint32_t filter_bit(unsigned long long cell, unsigned long long lo, bool hashed, uint32_t bits) {
     return hashed ? (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64 - bits)) : (uint32_t)(cell - lo);
 }
@@ -1266,9 +1344,10 @@ DEV bool sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t tb,
 
 // Decides the cnt records held in registers (element i = j * NT + thread;
 // lanes past the end hold a copy of a real record) with the LDS array a
-// (TILE_LDS words) as scratch.  Returns whether a cell races, with the
-// least racy cell and its witness pair.
-template <int E, int NT, uint32_t LW = TILE_LDS>
+// (LW words) as scratch.  Returns whether a cell races, with the least racy
+// cell and its witness pair.  SPLIT and B4 (hash insertion four records at
+// a time) are chosen per caller by its register budget.
+template <int E, int NT, uint32_t LW = TILE_LDS, bool SPLIT = false, bool B4 = true>
 DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, unsigned long long *a, uint32_t *red,
                 unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     using SC = Scratch<LW>;
@@ -1338,14 +1417,29 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
             red[RED_NC] = 0;
         }
         __syncthreads();
+        // rows four at a time, branch free within the four (a lane past the
+        // records sets a bit of a word of its own that no one reads), so
+        // that the four seen atomics are in flight together
         bool again = false;
+        uint32_t *const dummy = w32 + 2 * SC::fwords + lane_id();
 #pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, SC::fbits), bit = 1u << (b & 31);
-                if (atomicOr(&seen[b >> 5], bit) & bit) {
-                    atomicOr(&rep[b >> 5], bit);
-                    again = true;
+        for (int j0 = 0; j0 < E; j0 += 4) {
+            if ((uint32_t)j0 * NT < cnt) {
+                uint32_t old[4], bits[4], wd[4];
+#pragma unroll
+                for (int d = 0; d < 4 && j0 + d < E; d++) {
+                    const int j = j0 + d;
+                    const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, SC::fbits);
+                    bits[d] = 1u << (b & 31);
+                    wd[d] = b >> 5;
+                    old[d] = atomicOr((uint32_t)j * NT + threadIdx.x < cnt ? &seen[wd[d]] : dummy, bits[d]);
+                }
+#pragma unroll
+                for (int d = 0; d < 4 && j0 + d < E; d++) {
+                    if ((uint32_t)(j0 + d) * NT + threadIdx.x < cnt && (old[d] & bits[d])) {
+                        atomicOr(&rep[wd[d]], bits[d]);
+                        again = true;
+                    }
                 }
             }
         }
@@ -1371,24 +1465,88 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
     }
     const bool compact = nc <= SC::surv_cap;
     if (span <= 0xFFFFFFFFull) {
-        int r;
-        if (compact) {
-            // survivors spread over the threads, the table above them
-            auto src = [&](auto f) {
-                for (uint32_t i = threadIdx.x; i < nc; i += NT) f(a[ph(i)]);
-            };
-            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32 + SC::surv_words, (SC::words - SC::surv_words) / 4, red,
-                             key, i1, i2);
-        } else {
-            auto src = [&](auto f) {
+        // one hash pass over the survivors; when its table overflows, the
+        // cells are split four ways by a second hash of the cell and each
+        // part takes a pass of its own (the least racy cell over the parts
+        // is the least of all)
+        for (uint32_t nparts = 1; nparts <= (SPLIT ? 4u : 1u); nparts *= 4) {
+            bool over = false, found = false;
+            unsigned long long bk = ~0ull;
+            uint32_t b1 = 0, b2 = 0;
+            for (uint32_t q = 0; q < nparts; q++) {
+                auto part = [&](unsigned long long r) {
+                    return nparts == 1 || (((uint32_t)((r >> ish) - lo) * 0x85EBCA6Bu) >> 30) == q;
+                };
+                unsigned long long k2 = 0;
+                uint32_t j1 = 0, j2 = 0;
+                int r;
+                if (compact) {
+                    // survivors spread over the threads, the table above them
+                    auto src = [&](auto f) {
+                        if constexpr (B4) {
+                            for (uint32_t i = threadIdx.x; i < nc; i += 4 * NT) {
+                                unsigned long long x[4];
+                                uint32_t vm = 0;
 #pragma unroll
-                for (int j = 0; j < E; j++)
-                    if ((keepm >> j) & 1u) f(u[j]);
-            };
-            r = hash_agg<NT>(src, nc, ish, tmask, lo, w32, SC::hslots, red, key, i1, i2);
+                                for (int d = 0; d < 4; d++) {
+                                    const uint32_t id = i + (uint32_t)d * NT;
+                                    x[d] = a[ph(id < nc ? id : i)];
+                                    if (id < nc && part(x[d])) vm |= 1u << d;
+                                }
+                                if (vm) f(x, vm);
+                            }
+                        } else {
+                            for (uint32_t i = threadIdx.x; i < nc; i += NT) {
+                                const unsigned long long x = a[ph(i)];
+                                if (part(x)) f(x);
+                            }
+                        }
+                    };
+                    r = hash_agg<NT, B4>(src, nc, ish, tmask, lo, w32 + SC::surv_words, (SC::words - SC::surv_words) / 4,
+                                     red, k2, j1, j2);
+                } else {
+                    auto src = [&](auto f) {
+                        if constexpr (B4) {
+#pragma unroll
+                            for (int j0 = 0; j0 < E; j0 += 4) {
+                                unsigned long long x[4];
+                                uint32_t vm = 0;
+#pragma unroll
+                                for (int d = 0; d < 4; d++) {
+                                    x[d] = u[j0 + d < E ? j0 + d : j0];
+                                    if (j0 + d < E && ((keepm >> (j0 + d)) & 1u) && part(x[d])) vm |= 1u << d;
+                                }
+                                if (vm) f(x, vm);
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < E; j++)
+                                if (((keepm >> j) & 1u) && part(u[j])) f(u[j]);
+                        }
+                    };
+                    r = hash_agg<NT, B4>(src, nc, ish, tmask, lo, w32, SC::hslots, red, k2, j1, j2);
+                }
+                if (r < 0) {
+                    over = true;
+                    break;
+                }
+                if (r == 1 && k2 < bk) {
+                    found = true;
+                    bk = k2;
+                    b1 = j1;
+                    b2 = j2;
+                }
+            }
+            __syncthreads();   // every thread has seen the outcome
+            if (!over) {
+                if (found) {
+                    key = bk;
+                    i1 = b1;
+                    i2 = b2;
+                }
+                return found;
+            }
         }
-        if (r >= 0) return r == 1;
-        __syncthreads();   // every thread has seen the overflow
     }
     // sort the survivors (compacted to a[ph(0..nc))), padded to a power of two
     if (!compact) {
@@ -2100,7 +2258,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, const uint3
             __syncthreads();
             unsigned long long key = 0;
             uint32_t r1 = 0, r2 = 0;
-            const bool f = decide<FE, WG, FT_LDS>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
+            const bool f = decide<FE, WG, FT_LDS, true, false>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
             if (f && !have) {
                 have = true;
                 const uint64_t kk = gk0 + (pack ? (key >> pd.ib) : 0ull);
