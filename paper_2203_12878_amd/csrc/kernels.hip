@@ -1345,8 +1345,8 @@ DEV bool sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t tb,
 // Decides the cnt records held in registers (element i = j * NT + thread;
 // lanes past the end hold a copy of a real record) with the LDS array a
 // (LW words) as scratch.  Returns whether a cell races, with the least racy
-// cell and its witness pair.  SPLIT and B4 (hash insertion four records at
-// a time) are chosen per caller by its register budget.
+// cell and its witness pair.  SPLIT and B4 (table and hash updates four
+// records at a time) are chosen per caller by its register budget.
 template <int E, int NT, uint32_t LW = TILE_LDS, bool SPLIT = false, bool B4 = true>
 DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, unsigned long long *a, uint32_t *red,
                 unsigned long long &key, uint32_t &i1, uint32_t &i2) {
@@ -1370,11 +1370,37 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         uint32_t *t0 = w32, *w0 = w32 + sp, *t1 = w32 + 2 * sp;
         for (uint32_t k = threadIdx.x; k < 3 * sp; k += NT) w32[k] = NONE32;
         __syncthreads();
+        if constexpr (B4) {
+            // four rows at a time: the least-tid atomics in flight together,
+            // then the second-tid offers (cell_update, reordered)
 #pragma unroll
-        for (int j = 0; j < E; j++) {
-            if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
-                cell_update(t0 + b, t1 + b, w0 + b, tid, (u[j] & 1ull) != 0);
+            for (int j0 = 0; j0 < E; j0 += 4) {
+                if ((uint32_t)j0 * NT < cnt) {
+                    uint32_t bb[4], tid[4], old[4];
+#pragma unroll
+                    for (int d = 0; d < 4 && j0 + d < E; d++) {
+                        const int j = j0 + d;
+                        bb[d] = (uint32_t)((u[j] >> ish) - lo);
+                        tid[d] = (uint32_t)(u[j] >> 1) & tmask;
+                        old[d] = NONE32;
+                        if ((uint32_t)j * NT + threadIdx.x < cnt) {
+                            old[d] = atomicMin(t0 + bb[d], tid[d]);
+                            if (u[j] & 1ull) atomicMin(w0 + bb[d], tid[d]);
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < 4 && j0 + d < E; d++)
+                        if (old[d] != NONE32 && old[d] != tid[d])
+                            atomicMin(t1 + bb[d], old[d] > tid[d] ? old[d] : tid[d]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < E; j++) {
+                if ((uint32_t)j * NT + threadIdx.x < cnt) {
+                    const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
+                    cell_update(t0 + b, t1 + b, w0 + b, tid, (u[j] & 1ull) != 0);
+                }
             }
         }
         __syncthreads();
@@ -1446,18 +1472,45 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         if (again) red[RED_CAND] = 1;
         __syncthreads();
         if (red[RED_CAND] == 0) return false;   // every cell touched once
+        // the survivors (rows four at a time: their bitmap reads in flight
+        // together), then one reservation per wave for all of its survivors
+        // (each lane's count and prefix from its count's bits), written lane
+        // by lane
 #pragma unroll
-        for (int j = 0; j < E; j++) {
-            const uint32_t b = filter_bit(u[j] >> ish, lo, hashed, SC::fbits);
-            const bool keep = (uint32_t)j * NT + threadIdx.x < cnt && ((rep[b >> 5] >> (b & 31)) & 1u);
-            const uint64_t m = ballot(keep);
-            if (m) {
-                keepm |= (keep ? 1u : 0u) << j;
+        for (int j0 = 0; j0 < E; j0 += 4) {
+            if ((uint32_t)j0 * NT < cnt) {
+                uint32_t wv[4], bb[4];
+#pragma unroll
+                for (int d = 0; d < 4 && j0 + d < E; d++) {
+                    const uint32_t b = filter_bit(u[j0 + d] >> ish, lo, hashed, SC::fbits);
+                    bb[d] = b & 31;
+                    wv[d] = rep[b >> 5];
+                }
+#pragma unroll
+                for (int d = 0; d < 4 && j0 + d < E; d++)
+                    if ((uint32_t)(j0 + d) * NT + threadIdx.x < cnt && ((wv[d] >> bb[d]) & 1u)) keepm |= 1u << (j0 + d);
+            }
+        }
+        {
+            const uint32_t mine = (uint32_t)__builtin_popcount(keepm);
+            uint32_t tot = 0, excl = 0;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {   // mine <= 32
+                const uint64_t bk = ballot((mine >> k) & 1u);
+                tot += (uint32_t)__builtin_popcountll(bk) << k;
+                excl += mbcnt(bk) << k;
+            }
+            if (tot) {
                 uint32_t base = 0;
-                if (lane_id() == 0) base = atomicAdd(&red[RED_NC], (uint32_t)__builtin_popcountll(m));
-                base = __shfl(base, 0);
-                const uint32_t pos = base + mbcnt(m);
-                if (keep && pos < SC::surv_cap) a[ph(pos)] = u[j];
+                if (lane_id() == 0) base = atomicAdd(&red[RED_NC], tot);
+                uint32_t pos = readlane(base, 0) + excl;
+#pragma unroll
+                for (int j = 0; j < E; j++) {
+                    if ((keepm >> j) & 1u) {
+                        if (pos < SC::surv_cap) a[ph(pos)] = u[j];
+                        pos++;
+                    }
+                }
             }
         }
         __syncthreads();   // the bitmaps are read for the last time
