@@ -825,6 +825,43 @@ DEV void block_sort_e(unsigned long long *a, uint32_t n) {
     __syncthreads();
 }
 
+// Bitonic sort of a[0..n) (n a power of two, n >= 2) in LDS by an
+// NT-thread workgroup with every stage through LDS: no record stays in
+// registers between stages, and a thread holds four pairs at a time (for
+// callers at their register budget).
+template <int NT>
+DEV void block_sort_lds(unsigned long long *a, uint32_t n) {
+    const uint32_t half = n >> 1;
+    __syncthreads();
+    for (uint32_t size = 2; size <= n; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride >= 1; stride >>= 1) {
+            for (uint32_t i0 = threadIdx.x; i0 < half; i0 += 4 * NT) {
+                unsigned long long x[4], y[4];
+                uint32_t lo[4];
+#pragma unroll
+                for (int d = 0; d < 4; d++) {
+                    const uint32_t i = i0 + (uint32_t)d * NT;
+                    lo[d] = 2 * i - (i & (stride - 1));
+                    if (i < half) {
+                        x[d] = a[ph(lo[d])];
+                        y[d] = a[ph(lo[d] + stride)];
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < 4; d++) {
+                    if (i0 + (uint32_t)d * NT < half) {
+                        const bool asc = (lo[d] & size) == 0;
+                        const bool sw = (x[d] > y[d]) == asc;
+                        a[ph(lo[d])] = sw ? y[d] : x[d];
+                        a[ph(lo[d] + stride)] = sw ? x[d] : y[d];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Sorts a[0..npow) (npow a power of two, 256 <= npow <= TILE).
 DEV void block_sort(unsigned long long *a, uint32_t npow) {
     switch (npow >> 8) {
@@ -1105,11 +1142,12 @@ DEV void block_minmax64(unsigned long long &lo, unsigned long long &hi, uint32_t
 //          access cannot race).  When no cell repeats the group is race
 //          free; otherwise the records left are aggregated per cell as in
 //          the table method, in an LDS hash table.
-//  split   (SPLIT) when the survivors hold more distinct cells than the
+//  split   (LIGHT) when the survivors hold more distinct cells than the
 //          hash table takes, a second hash of the cell splits them four
 //          ways and each part takes a table pass of its own.
-//  sort    when a table still overflows (or without SPLIT): the survivors
-//          are sorted and scanned.
+//  sort    when a table still overflows (or without LIGHT): the survivors
+//          are sorted and scanned (with LIGHT by a sort whose stages all
+//          go through LDS).
 // Tiles run 512-thread workgroups: at most 16 records per thread stay in
 // registers, and the two workgroups the LDS admits per CU give 4 waves per
 // SIMD.
@@ -1178,13 +1216,12 @@ DEV void cell_update(uint32_t *t0, uint32_t *t1, uint32_t *w0, uint32_t tid, boo
 // least writing tid, least tid other than the first), the table sized for
 // twice the survivors.  Probing never takes more steps than there are
 // slots; more distinct cells than three quarters of the slots is an
-// overflow.  src(f) calls f(record) for each survivor this thread owns (the
-// same ones on every call); with B4 it calls f(r, vm) for them four at a
-// time (r[d] is one when bit d of vm is set), and the four records' atomics
-// are in flight together (more registers: the fused path, at its register
-// budget, takes records one by one).  Returns 1 (racy cell found), 0 (none)
-// or -1 (overflow: the caller falls back to another method).
-template <int NT, bool B4, class Src>
+// overflow.  src(f) calls f(r, vm) for the survivors this thread owns,
+// four at a time (r[d] is one when bit d of vm is set; the same ones on
+// every call), so that the four records' atomics are in flight together.
+// Returns 1 (racy cell found), 0 (none) or -1 (overflow: the caller falls
+// back to another method).
+template <int NT, class Src>
 DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsigned long long lo, uint32_t *mem,
                  uint32_t max_slots, uint32_t *red, unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     uint32_t hb = 8;
@@ -1199,107 +1236,78 @@ DEV int hash_agg(const Src &src, uint32_t nc, uint32_t ish, uint32_t tmask, unsi
     }
     __syncthreads();
     bool ovf = false;
-    if constexpr (B4) {
-        src([&](const unsigned long long (&r)[4], uint32_t vm) {
-            uint32_t c[4], h[4], o[4];
+    src([&](const unsigned long long (&r)[4], uint32_t vm) {
+        uint32_t c[4], h[4], o[4];
 #pragma unroll
-            for (int d = 0; d < 4; d++) {
-                c[d] = (uint32_t)((r[d] >> ish) - lo);
-                h[d] = (c[d] * 0x9E3779B1u) >> (32 - hb);
-                o[d] = NONE32;
-                if ((vm >> d) & 1u) o[d] = atomicCAS(&K[h[d]], NONE32, c[d]);
-            }
-            // a slot taken by another cell: probe on, one record at a time
-            uint32_t placed = 0, fresh = 0;
+        for (int d = 0; d < 4; d++) {
+            c[d] = (uint32_t)((r[d] >> ish) - lo);
+            h[d] = (c[d] * 0x9E3779B1u) >> (32 - hb);
+            o[d] = NONE32;
+            if ((vm >> d) & 1u) o[d] = atomicCAS(&K[h[d]], NONE32, c[d]);
+        }
+        // a slot taken by another cell: probe on, one record at a time
+        uint32_t placed = 0, fresh = 0;
 #pragma unroll
-            for (int d = 0; d < 4; d++) {
-                if (!((vm >> d) & 1u)) continue;
-                uint32_t old = o[d];
-                for (uint32_t st = 1; st < S && old != NONE32 && old != c[d]; st++) {
-                    h[d] = (h[d] + 1) & (S - 1);
-                    old = atomicCAS(&K[h[d]], NONE32, c[d]);
-                }
-                if (old == NONE32 || old == c[d]) {
-                    placed |= 1u << d;
-                    fresh += old == NONE32 ? 1u : 0u;
-                } else {
-                    ovf = true;
-                }
+        for (int d = 0; d < 4; d++) {
+            if (!((vm >> d) & 1u)) continue;
+            uint32_t old = o[d];
+            for (uint32_t st = 1; st < S && old != NONE32 && old != c[d]; st++) {
+                h[d] = (h[d] + 1) & (S - 1);
+                old = atomicCAS(&K[h[d]], NONE32, c[d]);
             }
-            // new cells of the wave counted by one atomic of its first active lane
-            const uint64_t b0 = ballot(fresh & 1u), b1 = ballot(fresh & 2u), b2 = ballot(fresh & 4u);
-            const uint32_t nf = (uint32_t)(__builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
-                                           4 * __builtin_popcountll(b2));
-            if (nf) {
-                const uint32_t leader = (uint32_t)__builtin_ctzll(ballot(true));
-                uint32_t base = 0;
-                if (lane_id() == leader) base = atomicAdd(&red[RED_CAND], nf);
-                base = readlane(base, leader);
-                if (base + nf > cap) ovf = true;
-            }
-            // the cells' aggregates (cell_update, four records at a time)
-            uint32_t t0o[4], tid[4];
-#pragma unroll
-            for (int d = 0; d < 4; d++) {
-                tid[d] = (uint32_t)(r[d] >> 1) & tmask;
-                t0o[d] = NONE32;
-                if ((placed >> d) & 1u) {
-                    t0o[d] = atomicMin(T0 + h[d], tid[d]);
-                    if (r[d] & 1ull) atomicMin(W0 + h[d], tid[d]);
-                }
-            }
-#pragma unroll
-            for (int d = 0; d < 4; d++)
-                if (((placed >> d) & 1u) && t0o[d] != NONE32 && t0o[d] != tid[d])
-                    atomicMin(T1 + h[d], t0o[d] > tid[d] ? t0o[d] : tid[d]);
-        });
-    } else {
-        src([&](unsigned long long r) {
-            const uint32_t c = (uint32_t)((r >> ish) - lo);
-            const uint32_t tid = (uint32_t)(r >> 1) & tmask;
-            uint32_t h = (c * 0x9E3779B1u) >> (32 - hb);
-            bool placed = false;
-            for (uint32_t st = 0; st < S; st++) {
-                const uint32_t old = atomicCAS(&K[h], NONE32, c);
-                if (old == NONE32 || old == c) {
-                    if (old == NONE32 && atomicAdd(&red[RED_CAND], 1u) >= cap) ovf = true;
-                    placed = true;
-                    break;
-                }
-                h = (h + 1) & (S - 1);
-            }
-            if (placed) {
-                cell_update(T0 + h, T1 + h, W0 + h, tid, (r & 1ull) != 0);
+            if (old == NONE32 || old == c[d]) {
+                placed |= 1u << d;
+                fresh += old == NONE32 ? 1u : 0u;
             } else {
                 ovf = true;
             }
-        });
-    }
+        }
+        // new cells of the wave counted by one atomic of its first active lane
+        const uint64_t b0 = ballot(fresh & 1u), b1 = ballot(fresh & 2u), b2 = ballot(fresh & 4u);
+        const uint32_t nf = (uint32_t)(__builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
+                                       4 * __builtin_popcountll(b2));
+        if (nf) {
+            const uint32_t leader = (uint32_t)__builtin_ctzll(ballot(true));
+            uint32_t base = 0;
+            if (lane_id() == leader) base = atomicAdd(&red[RED_CAND], nf);
+            base = readlane(base, leader);
+            if (base + nf > cap) ovf = true;
+        }
+        // the cells' aggregates (cell_update, four records at a time)
+        uint32_t t0o[4], tid[4];
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            tid[d] = (uint32_t)(r[d] >> 1) & tmask;
+            t0o[d] = NONE32;
+            if ((placed >> d) & 1u) {
+                t0o[d] = atomicMin(T0 + h[d], tid[d]);
+                if (r[d] & 1ull) atomicMin(W0 + h[d], tid[d]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; d++)
+            if (((placed >> d) & 1u) && t0o[d] != NONE32 && t0o[d] != tid[d])
+                atomicMin(T1 + h[d], t0o[d] > tid[d] ? t0o[d] : tid[d]);
+    });
+
     if (ovf) red[RED_OVF] = 1;
     __syncthreads();
     if (red[RED_OVF]) return -1;
     // least racy cell, with its slot in the low bits (a cell has one slot)
     unsigned long long best = ~0ull, none = 0;
-    if constexpr (B4) {
-        // four slots a thread per step
-        const uint4 *T14 = reinterpret_cast<const uint4 *>(T1), *W04 = reinterpret_cast<const uint4 *>(W0);
-        for (uint32_t q = threadIdx.x; q < S / 4; q += NT) {
-            const uint4 kv = K4[q], tv = T14[q], wv = W04[q];
-            const uint32_t kk[4] = {kv.x, kv.y, kv.z, kv.w}, tt[4] = {tv.x, tv.y, tv.z, tv.w},
-                           ww[4] = {wv.x, wv.y, wv.z, wv.w};
+    // four slots a thread per step
+    const uint4 *T14 = reinterpret_cast<const uint4 *>(T1), *W04 = reinterpret_cast<const uint4 *>(W0);
+    for (uint32_t q = threadIdx.x; q < S / 4; q += NT) {
+        const uint4 kv = K4[q], tv = T14[q], wv = W04[q];
+        const uint32_t kk[4] = {kv.x, kv.y, kv.z, kv.w}, tt[4] = {tv.x, tv.y, tv.z, tv.w},
+                       ww[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
-            for (int d = 0; d < 4; d++) {
-                const unsigned long long c = ((unsigned long long)kk[d] << 32) | (4 * q + (uint32_t)d);
-                if ((kk[d] != NONE32) & (tt[d] != NONE32) & (ww[d] != NONE32)) best = c < best ? c : best;
-            }
+        for (int d = 0; d < 4; d++) {
+            const unsigned long long c = ((unsigned long long)kk[d] << 32) | (4 * q + (uint32_t)d);
+            if ((kk[d] != NONE32) & (tt[d] != NONE32) & (ww[d] != NONE32)) best = c < best ? c : best;
         }
-    } else {
-        for (uint32_t k = threadIdx.x; k < S; k += NT)
-            if (K[k] != NONE32 && T1[k] != NONE32 && W0[k] != NONE32) {
-                const unsigned long long c = ((unsigned long long)K[k] << 32) | k;
-                best = c < best ? c : best;
-            }
     }
+
     block_minmax64(best, none, red);
     if (best == ~0ull) return 0;
     const uint32_t k = (uint32_t)best;
@@ -1345,9 +1353,9 @@ DEV bool sort_scan(unsigned long long *a, uint32_t n, uint32_t cnt, uint32_t tb,
 // Decides the cnt records held in registers (element i = j * NT + thread;
 // lanes past the end hold a copy of a real record) with the LDS array a
 // (LW words) as scratch.  Returns whether a cell races, with the least racy
-// cell and its witness pair.  SPLIT and B4 (table and hash updates four
-// records at a time) are chosen per caller by its register budget.
-template <int E, int NT, uint32_t LW = TILE_LDS, bool SPLIT = false, bool B4 = true>
+// cell and its witness pair.  LIGHT (the register-light fallbacks above)
+// is chosen per caller by its register budget.
+template <int E, int NT, uint32_t LW = TILE_LDS, bool LIGHT = false>
 DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, unsigned long long *a, uint32_t *red,
                 unsigned long long &key, uint32_t &i1, uint32_t &i2) {
     using SC = Scratch<LW>;
@@ -1370,37 +1378,27 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         uint32_t *t0 = w32, *w0 = w32 + sp, *t1 = w32 + 2 * sp;
         for (uint32_t k = threadIdx.x; k < 3 * sp; k += NT) w32[k] = NONE32;
         __syncthreads();
-        if constexpr (B4) {
-            // four rows at a time: the least-tid atomics in flight together,
-            // then the second-tid offers (cell_update, reordered)
+        // four rows at a time: the least-tid atomics in flight together,
+        // then the second-tid offers (cell_update, reordered)
 #pragma unroll
-            for (int j0 = 0; j0 < E; j0 += 4) {
-                if ((uint32_t)j0 * NT < cnt) {
-                    uint32_t bb[4], tid[4], old[4];
+        for (int j0 = 0; j0 < E; j0 += 4) {
+            if ((uint32_t)j0 * NT < cnt) {
+                uint32_t bb[4], tid[4], old[4];
 #pragma unroll
-                    for (int d = 0; d < 4 && j0 + d < E; d++) {
-                        const int j = j0 + d;
-                        bb[d] = (uint32_t)((u[j] >> ish) - lo);
-                        tid[d] = (uint32_t)(u[j] >> 1) & tmask;
-                        old[d] = NONE32;
-                        if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                            old[d] = atomicMin(t0 + bb[d], tid[d]);
-                            if (u[j] & 1ull) atomicMin(w0 + bb[d], tid[d]);
-                        }
+                for (int d = 0; d < 4 && j0 + d < E; d++) {
+                    const int j = j0 + d;
+                    bb[d] = (uint32_t)((u[j] >> ish) - lo);
+                    tid[d] = (uint32_t)(u[j] >> 1) & tmask;
+                    old[d] = NONE32;
+                    if ((uint32_t)j * NT + threadIdx.x < cnt) {
+                        old[d] = atomicMin(t0 + bb[d], tid[d]);
+                        if (u[j] & 1ull) atomicMin(w0 + bb[d], tid[d]);
                     }
-#pragma unroll
-                    for (int d = 0; d < 4 && j0 + d < E; d++)
-                        if (old[d] != NONE32 && old[d] != tid[d])
-                            atomicMin(t1 + bb[d], old[d] > tid[d] ? old[d] : tid[d]);
                 }
-            }
-        } else {
 #pragma unroll
-            for (int j = 0; j < E; j++) {
-                if ((uint32_t)j * NT + threadIdx.x < cnt) {
-                    const uint32_t b = (uint32_t)((u[j] >> ish) - lo), tid = (uint32_t)(u[j] >> 1) & tmask;
-                    cell_update(t0 + b, t1 + b, w0 + b, tid, (u[j] & 1ull) != 0);
-                }
+                for (int d = 0; d < 4 && j0 + d < E; d++)
+                    if (old[d] != NONE32 && old[d] != tid[d])
+                        atomicMin(t1 + bb[d], old[d] > tid[d] ? old[d] : tid[d]);
             }
         }
         __syncthreads();
@@ -1522,7 +1520,7 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
         // cells are split four ways by a second hash of the cell and each
         // part takes a pass of its own (the least racy cell over the parts
         // is the least of all)
-        for (uint32_t nparts = 1; nparts <= (SPLIT ? 4u : 1u); nparts *= 4) {
+        for (uint32_t nparts = 1; nparts <= (LIGHT ? 4u : 1u); nparts *= 4) {
             bool over = false, found = false;
             unsigned long long bk = ~0ull;
             uint32_t b1 = 0, b2 = 0;
@@ -1536,48 +1534,35 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
                 if (compact) {
                     // survivors spread over the threads, the table above them
                     auto src = [&](auto f) {
-                        if constexpr (B4) {
-                            for (uint32_t i = threadIdx.x; i < nc; i += 4 * NT) {
-                                unsigned long long x[4];
-                                uint32_t vm = 0;
+                        for (uint32_t i = threadIdx.x; i < nc; i += 4 * NT) {
+                            unsigned long long x[4];
+                            uint32_t vm = 0;
 #pragma unroll
-                                for (int d = 0; d < 4; d++) {
-                                    const uint32_t id = i + (uint32_t)d * NT;
-                                    x[d] = a[ph(id < nc ? id : i)];
-                                    if (id < nc && part(x[d])) vm |= 1u << d;
-                                }
-                                if (vm) f(x, vm);
+                            for (int d = 0; d < 4; d++) {
+                                const uint32_t id = i + (uint32_t)d * NT;
+                                x[d] = a[ph(id < nc ? id : i)];
+                                if (id < nc && part(x[d])) vm |= 1u << d;
                             }
-                        } else {
-                            for (uint32_t i = threadIdx.x; i < nc; i += NT) {
-                                const unsigned long long x = a[ph(i)];
-                                if (part(x)) f(x);
-                            }
+                            if (vm) f(x, vm);
                         }
                     };
-                    r = hash_agg<NT, B4>(src, nc, ish, tmask, lo, w32 + SC::surv_words, (SC::words - SC::surv_words) / 4,
+                    r = hash_agg<NT>(src, nc, ish, tmask, lo, w32 + SC::surv_words, (SC::words - SC::surv_words) / 4,
                                      red, k2, j1, j2);
                 } else {
                     auto src = [&](auto f) {
-                        if constexpr (B4) {
 #pragma unroll
-                            for (int j0 = 0; j0 < E; j0 += 4) {
-                                unsigned long long x[4];
-                                uint32_t vm = 0;
+                        for (int j0 = 0; j0 < E; j0 += 4) {
+                            unsigned long long x[4];
+                            uint32_t vm = 0;
 #pragma unroll
-                                for (int d = 0; d < 4; d++) {
-                                    x[d] = u[j0 + d < E ? j0 + d : j0];
-                                    if (j0 + d < E && ((keepm >> (j0 + d)) & 1u) && part(x[d])) vm |= 1u << d;
-                                }
-                                if (vm) f(x, vm);
+                            for (int d = 0; d < 4; d++) {
+                                x[d] = u[j0 + d < E ? j0 + d : j0];
+                                if (j0 + d < E && ((keepm >> (j0 + d)) & 1u) && part(x[d])) vm |= 1u << d;
                             }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < E; j++)
-                                if (((keepm >> j) & 1u) && part(u[j])) f(u[j]);
+                            if (vm) f(x, vm);
                         }
                     };
-                    r = hash_agg<NT, B4>(src, nc, ish, tmask, lo, w32, SC::hslots, red, k2, j1, j2);
+                    r = hash_agg<NT>(src, nc, ish, tmask, lo, w32, SC::hslots, red, k2, j1, j2);
                 }
                 if (r < 0) {
                     over = true;
@@ -1621,7 +1606,12 @@ DEV bool decide(const unsigned long long (&u)[E], uint32_t cnt, uint32_t tb, uns
     while (np < nc) np <<= 1;
     for (uint32_t k = nc + threadIdx.x; k < np; k += NT) a[ph(k)] = ~0ull;
     __syncthreads();
-    return sort_scan<NT, LW>(a, np, nc, tb, red, key, i1, i2);
+    if constexpr (LIGHT) {
+        block_sort_lds<NT>(a, np);
+        return block_first_racy(a, nc, tb, red, key, i1, i2);
+    } else {
+        return sort_scan<NT, LW>(a, np, nc, tb, red, key, i1, i2);
+    }
 }
 
 // =============================================================== fused path
@@ -2311,7 +2301,7 @@ DEV void fused_body(const Unit *__restrict__ units, uint32_t nunits, const uint3
             __syncthreads();
             unsigned long long key = 0;
             uint32_t r1 = 0, r2 = 0;
-            const bool f = decide<FE, WG, FT_LDS, true, false>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
+            const bool f = decide<FE, WG, FT_LDS, true>(v, cnt, tb, lds_rec, lds_res, key, r1, r2);
             if (f && !have) {
                 have = true;
                 const uint64_t kk = gk0 + (pack ? (key >> pd.ib) : 0ull);

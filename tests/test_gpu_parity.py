@@ -132,6 +132,9 @@ def test_mixed_batch_subset(chk):
         assert g.status == 0 and g.racy == (lab != "drf"), lab
 
 
+BIGCELL = "(+ (* x 33554432) (mod tid 16))"   # eight threads a cell, phases 2^25 apart
+
+
 def test_decision_fallbacks(chk):
     # one group whose survivors hold more distinct cells than the LDS hash
     # table takes (each cell read twice by one thread): the survivors are
@@ -141,10 +144,16 @@ def test_decision_fallbacks(chk):
              # packed groups whose cells span more than 2^32 (phase above a
              # 31-bit index): repeated cells are sorted without the hash table
              ("(fors x 0 64 (seq (rd (* x 33554432)) (sync)))", 2),
-             ("(fors x 0 64 (seq (if (= tid 1) (wr (* x 33554432)) (rd (* x 33554432))) (sync)))", 2)]
+             ("(fors x 0 64 (seq (if (= tid 1) (wr (* x 33554432)) (rd (* x 33554432))) (sync)))", 2),
+             # the same with a full group (64 phases of 128 records, 8192
+             # sorted at once), race free and racy at phase 50 only
+             ("(fors x 0 64 (seq (rd %s) (sync)))" % BIGCELL, 128),
+             ("(fors x 0 64 (seq (if (= x 50) (if (= tid 3) (wr %s) (rd %s)) (rd %s)) (sync)))" % (BIGCELL, BIGCELL, BIGCELL),
+              128)]
     got = chk.check_batch(items)
     _same(got, o2.check_many(items, jobs=4), items)
-    assert [g.racy for g in got] == [0, 1, 0, 1]
+    assert [g.racy for g in got] == [0, 1, 0, 1, 0, 1]
+    assert got[5].witness == (50, 50 * 33554432 + 3, 3, 19)
 
 
 def test_multi_block_items(chk):
