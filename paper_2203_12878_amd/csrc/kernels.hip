@@ -2342,6 +2342,23 @@ __global__ __launch_bounds__(WG) void k_fused64(FUSED_PARAMS) { fused_body<uint6
 #undef FUSED_ARGS
 
 // =============================================================== partition
+// Runs of equal digits in consecutive lanes of a wave whose valid lanes are
+// [0, nv): whether this lane heads a run, the run's length (on its head)
+// and the run's head lane (on every lane).  Records arrive in emission
+// order, so neighbouring lanes often share a digit: one atomic per run then
+// replaces one per lane (atomics on one address serialize).
+DEV void digit_runs(uint32_t d, uint32_t nv, bool &head, uint32_t &len, uint32_t &hl) {
+    const uint32_t l = lane_id();
+    const uint32_t dp = __shfl_up(d, 1u);
+    head = l < nv && (l == 0 || dp != d);
+    const uint64_t H = ballot(head);
+    const uint64_t after = H & bits_from(l + 1);
+    const uint32_t nh = after ? ctz64(after) : 64u;
+    len = (nh < nv ? nh : nv) - l;
+    const uint64_t upto = H & ~bits_from(l + 1);
+    hl = upto ? 63u - (uint32_t)__builtin_clzll(upto) : 0u;
+}
+
 __global__ __launch_bounds__(WG) void k_hist(const Seg *__restrict__ segs, const Chunk *__restrict__ chunks,
                                               const unsigned long long *__restrict__ in,
                                               unsigned long long *__restrict__ hist) {
@@ -2360,20 +2377,16 @@ __global__ __launch_bounds__(WG) void k_hist(const Seg *__restrict__ segs, const
         const uint32_t i = (uint32_t)j * WG + threadIdx.x;
         r[j] = in[b + (i < n ? i : n - 1)];
     }
-    // records arrive in emission order, so a wave's lanes often share one
-    // digit: then one atomic adds them all (otherwise 64 atomics on one
-    // address would serialize)
+    // one atomic per run of equal digits
 #pragma unroll
     for (int j = 0; j < CHUNK / WG; j++) {
-        const bool v = (uint32_t)j * WG + threadIdx.x < n;
+        const bool v = (uint32_t)j * WG + threadIdx.x < n;   // the valid lanes are a prefix
         const uint32_t d = (rec_idx(r[j]) >> sg.shift) & mask;
-        const uint64_t act = ballot(v);
-        const uint32_t d0 = readlane(d, act ? ctz64(act) : 0u);
-        if (act && ballot(v && d == d0) == act) {
-            if (lane_id() == ctz64(act)) atomicAdd(&h[d0], (uint32_t)__builtin_popcountll(act));
-        } else if (v) {
-            atomicAdd(&h[d], 1u);
-        }
+        const uint32_t nv = (uint32_t)__builtin_popcountll(ballot(v));
+        bool head;
+        uint32_t len, hl;
+        digit_runs(d, nv, head, len, hl);
+        if (head) atomicAdd(&h[d], len);
     }
     __syncthreads();
     const uint32_t nd = 1u << sg.dbits;
@@ -2463,21 +2476,19 @@ __global__ __launch_bounds__(WG) void k_scatter(const Seg *__restrict__ segs, co
         const uint32_t i = (uint32_t)j * WG + threadIdx.x;
         r[j] = in[b + (i < n ? i : n - 1)];
     }
+    // one reservation per run of equal digits; a run's records go to
+    // consecutive positions
 #pragma unroll
     for (int j = 0; j < CHUNK / WG; j++) {
-        const bool v = (uint32_t)j * WG + threadIdx.x < n;
+        const bool v = (uint32_t)j * WG + threadIdx.x < n;   // the valid lanes are a prefix
         const uint32_t d = (rec_idx(r[j]) >> sg.shift) & mask;
-        const uint64_t act = ballot(v);
-        const uint32_t d0 = readlane(d, act ? ctz64(act) : 0u);
-        uint32_t o = 0;
-        if (act && ballot(v && d == d0) == act) {
-            // one reservation for the whole wave (same digit everywhere)
-            uint32_t b0 = 0;
-            if (lane_id() == ctz64(act)) b0 = atomicAdd(&cur[d0], (uint32_t)__builtin_popcountll(act));
-            o = readlane(b0, ctz64(act)) + mbcnt(act);
-        } else if (v) {
-            o = atomicAdd(&cur[d], 1u);
-        }
+        const uint32_t nv = (uint32_t)__builtin_popcountll(ballot(v));
+        bool head;
+        uint32_t len, hl;
+        digit_runs(d, nv, head, len, hl);
+        uint32_t b0 = 0;
+        if (head) b0 = atomicAdd(&cur[d], len);
+        const uint32_t o = (uint32_t)__shfl((int)b0, (int)hl) + (lane_id() - hl);
         if (v && base[d] + o < cap) out[base[d] + o] = r[j];
     }
 }
