@@ -342,6 +342,17 @@ struct Call {
         upload(keep, dst, v, st);
         return (T *)dst;
     }
+    // upload n elements that fill(dst) writes straight into the staging
+    // memory (no intermediate vector)
+    template <class T, class F>
+    T *put_fill(void *region, size_t n, F fill) {
+        if (n == 0) return (T *)region;
+        void *dst = rec ? rec->alloc(n * sizeof(T)) : region;
+        void *h = keep.take(n * sizeof(T));
+        fill((T *)h);
+        hipck(hipMemcpyAsync(dst, h, n * sizeof(T), hipMemcpyHostToDevice, st));
+        return (T *)dst;
+    }
     void sync() {
         hipck(hipStreamSynchronize(st));
         keep.clear();
@@ -947,14 +958,18 @@ void run_table_waves(Call &C, const std::vector<BigPhase> &tbig, uint64_t cap_wo
 }
 
 // Fused units in launch order: largest first by the power of two of their
-// work, input order within one power (a counting sort, linear in the units).
-std::vector<Unit> order_units(const std::vector<Unit> &units, const std::vector<uint64_t> &work) {
+// work, input order within one power (a counting sort, linear in the units),
+// written to out[0 .. units.size()).
+void order_units_to(const std::vector<Unit> &units, const std::vector<uint64_t> &work, Unit *out) {
     auto bucket = [](uint64_t w) { return w ? 64 - __builtin_clzll(w) : 0; };
-    std::vector<size_t> start(66, 0);
+    size_t start[66] = {};
     for (uint64_t w : work) start[65 - bucket(w)]++;
-    for (size_t b = 1; b < start.size(); b++) start[b] += start[b - 1];
-    std::vector<Unit> out(units.size());
+    for (size_t b = 1; b < 66; b++) start[b] += start[b - 1];
     for (size_t i = 0; i < units.size(); i++) out[start[64 - bucket(work[i])]++] = units[i];
+}
+std::vector<Unit> order_units(const std::vector<Unit> &units, const std::vector<uint64_t> &work) {
+    std::vector<Unit> out(units.size());
+    order_units_to(units, work, out.data());
     return out;
 }
 
@@ -1070,11 +1085,17 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         auto fused = [&](std::vector<Unit> &units, bool wide, size_t dst_off, const std::vector<uint64_t> &work,
                          uint64_t events) {
             if (units.empty()) return;
-            const std::vector<Unit> ord = order_units(units, work);
+            // one launch (the common case): the ordered units go straight
+            // into the upload's staging memory
+            std::vector<Unit> ord;
+            if (units.size() > CAND_CAP) ord = order_units(units, work);
             for (uint64_t b0 = 0; b0 < units.size(); b0 += CAND_CAP) {
                 const uint64_t n = std::min<uint64_t>(units.size() - b0, CAND_CAP);
-                std::vector<Unit> part(ord.begin() + b0, ord.begin() + b0 + n);
-                const Unit *du = C.put(at<void>(A, dst_off), part);
+                const Unit *du =
+                    ord.empty() ? C.put_fill<Unit>(at<void>(A, dst_off), n,
+                                                   [&](Unit *d) { order_units_to(units, work, d); })
+                                : C.put(at<void>(A, dst_off),
+                                        std::vector<Unit>(ord.begin() + b0, ord.begin() + b0 + n));
                 if (qslot >= 64) {
                     C.fill32(qhead, 0, 64 * sizeof(uint32_t));
                     qslot = 0;
