@@ -614,8 +614,8 @@ DEV void emit_cal(const Item &it, const NestDesc &nd, const ProtoDesc &pd, const
         __syncthreads();
         // the item's tid blocks reuse the chunk's staging; EB iterations at
         // a time: their reservations are issued together and each access
-        // header is read once for all of them
-        constexpr uint32_t EB = 4;
+        // header is read once for all of them (eight measured best)
+        constexpr uint32_t EB = 8;
         for (uint32_t blk = 0; blk < it.nblk; blk++) {
             const uint32_t tid0 = it.tid0 + blk * (uint32_t)WG;
             const uint32_t tid = tid0 + threadIdx.x;
