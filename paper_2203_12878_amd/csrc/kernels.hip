@@ -862,18 +862,6 @@ DEV void block_sort_lds(unsigned long long *a, uint32_t n) {
     }
 }
 
-// Sorts a[0..npow) (npow a power of two, 256 <= npow <= TILE).
-DEV void block_sort(unsigned long long *a, uint32_t npow) {
-    switch (npow >> 8) {
-    case 1: block_sort_e<1>(a, npow); break;
-    case 2: block_sort_e<2>(a, npow); break;
-    case 4: block_sort_e<4>(a, npow); break;
-    case 8: block_sort_e<8>(a, npow); break;
-    case 16: block_sort_e<16>(a, npow); break;
-    default: block_sort_e<32>(a, npow); break;
-    }
-}
-
 DEV uint32_t rec_idx(unsigned long long r) { return (uint32_t)(r >> 32); }
 DEV uint32_t rec_tid(unsigned long long r) { return (uint32_t)(r >> 1) & 0x7FFFFFFFu; }
 
