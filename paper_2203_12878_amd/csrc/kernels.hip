@@ -1075,24 +1075,6 @@ DEV unsigned long long wave_max64(unsigned long long v) {
     }
     return v;
 }
-template <bool MAX>
-DEV unsigned long long block_ext64(unsigned long long v, uint32_t *red) {
-    v = MAX ? wave_max64(v) : wave_min64(v);
-    __syncthreads();
-    if (lane_id() == 0) {
-        red[2 * (threadIdx.x >> 6)] = (uint32_t)v;
-        red[2 * (threadIdx.x >> 6) + 1] = (uint32_t)(v >> 32);
-    }
-    __syncthreads();
-    unsigned long long r = ((unsigned long long)red[1] << 32) | red[0];
-    for (uint32_t w = 1; w < (blockDim.x >> 6); w++) {
-        const unsigned long long x = ((unsigned long long)red[2 * w + 1] << 32) | red[2 * w];
-        r = MAX ? (x > r ? x : r) : (x < r ? x : r);
-    }
-    __syncthreads();
-    return r;
-}
-
 // Workgroup min and max of a u64 in one reduction (red[0 .. 4 * waves)).
 DEV void block_minmax64(unsigned long long &lo, unsigned long long &hi, uint32_t *red) {
     lo = wave_min64(lo);
