@@ -1059,8 +1059,7 @@ DEV uint32_t block_min(uint32_t v, uint32_t *red) {
     return r;
 }
 
-// Workgroup min / max of a u64 through red[0 .. 2 * waves) (barriers on
-// entry and exit).
+// Wave min / max of a u64 (a butterfly over the 64 lanes).
 DEV unsigned long long wave_min64(unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long w = __shfl_xor(v, o);
