@@ -9,7 +9,8 @@ oracle), on the full synthetic workloads:
   batch (2048 instances) in one batched check each, with the big phases
   partitioned and (a second time) with the dense ones decided by tables;
 * a served Poisson stream at 5k req/s (1000 requests drawn 70/30 from the
-  mixed and tree generators), every request against its stored result.
+  mixed and tree generators), every request against its stored result;
+* a whole mixed batch at another seed against the oracle run in the test.
 
 Every field is compared exactly: status, race flag, witness, record
 count, number of phases and the per-phase counts (in full when stored,
@@ -98,6 +99,23 @@ def test_tree_batch_full(chk, table_bits):
         chk.set_tuning(table_bits=255)
     bad = _mismatches(got, exp)
     assert not bad, "%d of %d differ, first %r" % (len(bad), len(items), bad[:2])
+
+
+def test_mixed_batch_new_seed_live_oracle(chk):
+    """A whole mixed batch at a seed with no stored results: every protocol
+    below 2e7 events (about 3.7e9 events in all) against the C oracle run
+    now, and every protocol's verdict against the race its generator built
+    in (or not)."""
+    from oracle import o2
+    batch = w.gen_mixed_batch(7, 4096)
+    items = [(t, n) for t, n, _ in batch]
+    got = chk.check_batch(items)
+    sel = [i for i, r in enumerate(got) if r.num_records < 20_000_000]
+    assert len(sel) > 3500
+    want = o2.check_many([items[i] for i in sel], jobs=16)
+    bad = [items[i][0][:80] for i, e in zip(sel, want) if got[i].key() != e.key()]
+    assert not bad, "%d of %d differ, first %r" % (len(bad), len(sel), bad[:2])
+    assert all(g.status == 0 and g.racy == (lab != "drf") for (t, n, lab), g in zip(batch, got))
 
 
 def test_served_stream_matches_oracle():
