@@ -93,7 +93,11 @@
  * protocols need no wait at all), once per partition level of phases
  * above one tile (the host packs the next tiles from the bucket starts
  * while the scatter runs), and, at the start of a call, for the same
- * context's previous call (its pinned staging is reused).  `stream` must be
+ * context's previous call (its pinned staging is reused).  Part of a
+ * call's work may run on a second stream that the context owns (the fused
+ * decision of counted small phases, beside the partition of the big ones);
+ * the call's stream waits for it before the results are written, so
+ * synchronizing `stream` covers it.  `stream` must be
  * a live stream of the context's device (HIP does not validate handles: a
  * stale or made-up one is undefined behaviour, as in HIP itself).
  */
@@ -330,7 +334,8 @@ int drf_babycuda_infer(const char *text, size_t len, const char *params, char *o
                        int32_t *status);
 
 /* Per-kernel timing of a context (for measurement).  When enabled, every
- * kernel launch is bracketed by HIP events recorded on the call's stream;
+ * kernel launch is bracketed by HIP events recorded on the stream it runs on
+ * (the call's, or the context's second stream);
  * elapsed times are added up per kernel class once the call's work is
  * complete.  `records` counts the access events the class processed and
  * `bytes` its algorithmic HBM traffic (records written or read once at

@@ -57,6 +57,10 @@ struct drf_ctx {
     hipEvent_t done = nullptr;
     hipEvent_t counted = nullptr;
     hipEvent_t parted = nullptr;        // a partition level's bucket starts are on the host
+    // the counted protocols' fused units beside the HBM path (created on
+    // first use): their stream, its start and its end
+    hipStream_t side = nullptr;
+    hipEvent_t side_go = nullptr, side_done = nullptr;
     void *h_starts = nullptr;           // pinned host copy of those starts
     size_t h_starts_cap = 0;
     // pinned host staging of uploads and read-backs: blocks kept for the
@@ -99,6 +103,8 @@ struct Trace {
 
 
 constexpr uint64_t CAND_CAP = 1ull << 20;      // candidates per launch
+constexpr bool FUSED_BESIDE = true;            // counted fused units beside the HBM path
+constexpr uint64_t BESIDE_MIN = 1ull << 24;    // ... when both sides hold at least this many events
 constexpr uint64_t ALIGN = 256;
 
 struct Bump {
@@ -375,6 +381,8 @@ struct Call {
     Keep keep;
 
     // pool A offsets
+    bool beside = false;       // pool A holds the counted units' own witness candidates:
+    size_t o_best2, o_cand2;   // ... when they run beside the HBM path
     size_t o_protos, o_nests, o_fixed, o_code, o_items[2], o_itemcnt, o_ovf, o_nrec, o_qhead, o_best, o_cand, o_units,
         o_sunits[2], o_rin, o_res;
     size_t needA = 0;
@@ -523,7 +531,9 @@ struct Call {
         }
     }
 
-    void layout_a(uint64_t nunits_max) {
+    // (beside: room for the counted units' own witness candidates, which
+    // ordinary calls run on the context's second stream)
+    void layout_a(uint64_t nunits_max, bool beside) {
         Bump b;
         o_protos = b.reserve(protos.size() * sizeof(ProtoDesc));
         o_nests = b.reserve(nests.size() * sizeof(NestDesc));
@@ -538,6 +548,12 @@ struct Call {
         o_best = b.reserve(count * sizeof(Best));
         o_cand = b.reserve(CAND_CAP * sizeof(Cand));
         o_units = b.reserve(std::min<uint64_t>(nunits_max, CAND_CAP) * sizeof(Unit));
+        o_best2 = o_cand2 = 0;
+        this->beside = beside;
+        if (beside) {
+            o_best2 = b.reserve(count * sizeof(Best));
+            o_cand2 = b.reserve(std::min<uint64_t>(nunits_max, CAND_CAP) * sizeof(Cand));
+        }
         o_sunits[0] = b.reserve(sunits[0].size() * sizeof(Unit));
         o_sunits[1] = b.reserve(sunits[1].size() * sizeof(Unit));
         o_rin = b.reserve(count * sizeof(ResultIn));
@@ -1006,7 +1022,7 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
         C.tr.mark("blob", C.items[0].size() + C.items[1].size());
         if (C.total_phases > phase_cap || (C.total_phases && !d_phase_counts)) return DRF_E_ARG;
         // upper bound on fused units: one per small phase at most
-        C.layout_a(C.total_phases + 1);
+        C.layout_a(C.total_phases + 1, !noalloc && !rec);
         // the previous call's device work may still read the pinned staging
         // and read-back buffers: wait for it on the host before reusing them
         // (planning above overlapped with it)
@@ -1078,13 +1094,20 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                      {nrec_dev, 0u, count * sizeof(uint64_t)},
                      {qhead, 0u, 64 * sizeof(uint32_t)}});
         const uint32_t fgrid = ctx->cus * 2;
+        bool overlap = false;   // the counted units on the second stream
         const uint32_t small = small_events(ctx);
         int qslot = 0;
 
         // fused launches (persistent, units largest first), pair pick after each
+        // (side: on the context's second stream, one workgroup per CU, with
+        // their own witness candidates; the call's stream does the HBM path
+        // meanwhile)
         auto fused = [&](std::vector<Unit> &units, bool wide, size_t dst_off, const std::vector<uint64_t> &work,
-                         uint64_t events) {
+                         uint64_t events, bool side = false) {
             if (units.empty()) return;
+            Cand *fc = side ? at<Cand>(A, C.o_cand2) : cand;
+            Best *fb = side ? at<Best>(A, C.o_best2) : best;
+            const uint32_t fg = side ? ctx->cus : fgrid;
             // one launch (the common case): the ordered units go straight
             // into the upload's staging memory
             std::vector<Unit> ord;
@@ -1101,17 +1124,29 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                     qslot = 0;
                 }
                 uint32_t *qh = qhead + qslot++;
+                if (side) {
+                    // after everything the call's stream has queued so far
+                    hipck(hipEventRecord(ctx->side_go, st));
+                    hipck(hipStreamWaitEvent(ctx->side, ctx->side_go, 0));
+                    Prof pr(ctx, ctx->side, K_FUSED, events, 0);
+                    events = 0;
+                    hipck(launch_fused(du, (uint32_t)n, qh, wide, dnests, dprotos, dfixed, dcode, phase_counts, nrec_dev,
+                                       ovf, fc, fb, fg, small, ctx->side));
+                    hipck(launch_pick(fc, n, fb, ctx->side));
+                    hipck(hipEventRecord(ctx->side_done, ctx->side));
+                    continue;
+                }
                 {
                     Prof pr(ctx, st, K_FUSED, events, 0);
                     events = 0;
                     C.dev([=](hipStream_t s) {
                         return launch_fused(du, (uint32_t)n, qh, wide, dnests, dprotos, dfixed, dcode, phase_counts,
-                                            nrec_dev, ovf, cand, best, fgrid, small, s);
+                                            nrec_dev, ovf, fc, fb, fg, small, s);
                     });
                 }
                 {
                     Prof pr(ctx, st, K_OTHER, 0, 0);
-                    C.dev([=](hipStream_t s) { return launch_pick(cand, n, best, s); });
+                    C.dev([=](hipStream_t s) { return launch_pick(fc, n, fb, s); });
                 }
                 if (b0 + CAND_CAP < units.size()) C.sync();
             }
@@ -1229,16 +1264,34 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 for (uint32_t i = 0; i < count; i++) tot += nrec[i];
                 for (auto &pp : ctx->pending) if (pp.cls == K_COUNT) { pp.records = tot; break; }
             }
+            std::vector<uint64_t> work[2];
+            uint64_t ev[2] = {0, 0};
             for (int w = 0; w < 2; w++) {
-                std::vector<uint64_t> work(units[w].size());
-                uint64_t ev = 0;
-                for (size_t j = 0; j < work.size(); j++) {
+                work[w].assign(units[w].size(), 0);
+                for (size_t j = 0; j < work[w].size(); j++) {
                     for (uint64_t k = units[w][j].k0; k < units[w][j].k1; k++)
-                        if (counts[k] <= (uint64_t)small) work[j] += counts[k];
-                    ev += work[j];
+                        if (counts[k] <= (uint64_t)small) work[w][j] += counts[k];
+                    ev[w] += work[w][j];
                 }
-                fused(units[w], w == 1, C.o_units, work, ev);
             }
+            // the counted units run beside the HBM path when both are large
+            // (one launch of units at most, narrow or wide: the second
+            // stream's candidates hold one launch; not in recorded or
+            // allocation-free calls)
+            uint64_t big_recs = 0;
+            for (const BigPhase &bp : big) big_recs += bp.count;
+            overlap = FUSED_BESIDE && C.beside && ev[0] + ev[1] >= BESIDE_MIN && big_recs >= BESIDE_MIN &&
+                      qslot + 2 <= 64 && units[0].size() <= CAND_CAP && units[1].size() <= CAND_CAP &&
+                      (units[0].empty() || units[1].empty());
+            if (overlap && !ctx->side) {
+                hipck(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+                hipck(hipEventCreateWithFlags(&ctx->side_go, hipEventDisableTiming));
+                hipck(hipEventCreateWithFlags(&ctx->side_done, hipEventDisableTiming));
+            }
+            if (overlap) C.fill32(at<Best>(A, C.o_best2), 0xFFFFFFFFu, count * sizeof(Best));
+            C.tr.mark("counted events", ev[0] + ev[1]);
+            C.tr.mark("big-phase records", big_recs);
+            for (int w = 0; w < 2; w++) fused(units[w], w == 1, C.o_units, work[w], ev[w], overlap);
             C.tr.mark("fused launched", units[0].size() + units[1].size());
         }
 
@@ -1337,6 +1390,12 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             for (const Wave &W : waves) run_wave(C, big, W, best, cand);
             C.tr.mark("waves done");
         }
+        if (overlap) {
+            // join the second stream; its witnesses into the call's
+            hipck(hipStreamWaitEvent(st, ctx->side_done, 0));
+            Best *b2 = at<Best>(A, C.o_best2);
+            C.dev([=](hipStream_t s) { return launch_best_min(best, b2, count, s); });
+        }
 
         // ---- results
         std::vector<ResultIn> rin(count);
@@ -1364,9 +1423,11 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
     } catch (Fail f) {
         (void)hipGetLastError();
         (void)hipStreamSynchronize(st);
+        if (ctx->side) (void)hipStreamSynchronize(ctx->side);
         return f.code;
     } catch (...) {
         (void)hipStreamSynchronize(st);
+        if (ctx->side) (void)hipStreamSynchronize(ctx->side);
         return DRF_E_NOMEM;
     }
 }
@@ -1389,7 +1450,7 @@ uint64_t scratch_estimate(const drf_ctx *tuned, std::vector<Plan> &&plans) {
     C.count = (uint32_t)plans.size();
     C.plans = std::move(plans);
     C.build_blob();
-    C.layout_a(C.total_phases + 1);
+    C.layout_a(C.total_phases + 1, true);
     const uint32_t small = small_events(&tmp);
     uint64_t bigrec = 0, nbig = 0;
     for (const Plan &p : C.plans) {
@@ -1563,6 +1624,9 @@ int drf_ctx_destroy(drf_ctx *ctx) {
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->counted) (void)hipEventDestroy(ctx->counted);
     if (ctx->parted) (void)hipEventDestroy(ctx->parted);
+    if (ctx->side_go) (void)hipEventDestroy(ctx->side_go);
+    if (ctx->side_done) (void)hipEventDestroy(ctx->side_done);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->h_starts) (void)hipHostFree(ctx->h_starts);
     for (auto &b : ctx->pin_blocks) (void)hipHostFree(b.first);
     if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);

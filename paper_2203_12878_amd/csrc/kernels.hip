@@ -2769,6 +2769,17 @@ hipError_t launch_result(uint32_t count, const ResultIn *rin, const Best *best, 
                   out);
 }
 
+__global__ __launch_bounds__(WG) void k_best_min(Best *__restrict__ best, const Best *__restrict__ best2,
+                                                  uint32_t count) {
+    const uint32_t p = blockIdx.x * WG + threadIdx.x;
+    if (p < count && best2[p].key < best[p].key) best[p] = best2[p];
+}
+
+hipError_t launch_best_min(Best *best, const Best *best2, uint32_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    return launch(k_best_min, dim3((count + WG - 1) / WG), dim3(WG), s, best, best2, count);
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint64_t blocks = (n + 255) / 256;

@@ -113,6 +113,8 @@ hipError_t launch_single(const Group *groups, uint32_t ngroups, const unsigned l
 hipError_t launch_pick(const Cand *cands, uint64_t ncands, Best *best, hipStream_t s,
                        const uint32_t *n_dev = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
+// best[p] = the lesser of best[p] and best2[p] by key (with its pair)
+hipError_t launch_best_min(Best *best, const Best *best2, uint32_t count, hipStream_t s);
 
 // Up to FILL_MAX word fills in one launch (passed by value).
 constexpr int FILL_MAX = 8;
