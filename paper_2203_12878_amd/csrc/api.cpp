@@ -680,6 +680,8 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
     }
 
     C.tr.mark("wave emit launched", recs);
+    // (more groups than candidate slots: launches of at most CAND_CAP
+    // groups, each followed by its pick, in stream order without host waits)
     auto run_groups = [&](const std::vector<Group> &groups, const unsigned long long *recbuf) {
         for (uint64_t g0 = 0; g0 < groups.size(); g0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(groups.size() - g0, CAND_CAP);
@@ -698,9 +700,12 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
                 Prof pr(ctx, st, K_OTHER, 0, 0);
                 C.dev([=](hipStream_t s) { return launch_pick(cand, n, best, s); });
             }
-            C.sync();
         }
     };
+    // (as for the groups above: launches of at most CAND_CAP tiles, each
+    // followed by its pick; stream order keeps a launch from writing
+    // candidates or tile lists that the previous one still reads, so the
+    // host does not wait between them)
     auto run_tiles = [&](const std::vector<Tile> &tiles, const unsigned long long *recbuf) {
         for (uint64_t t0 = 0; t0 < tiles.size(); t0 += CAND_CAP) {
             const uint64_t n = std::min<uint64_t>(tiles.size() - t0, CAND_CAP);
@@ -717,7 +722,6 @@ void run_wave(Call &C, const std::vector<BigPhase> &big, const Wave &W, Best *be
                 Prof pr(ctx, st, K_OTHER, 0, 0);
                 C.dev([=](hipStream_t s) { return launch_pick(cand, n, best, s); });
             }
-            if (t0 + CAND_CAP < tiles.size()) C.sync();
         }
     };
 
