@@ -1279,12 +1279,17 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
                 }
             }
             // the counted units run beside the HBM path when both are large
-            // (one launch of units at most, narrow or wide: the second
-            // stream's candidates hold one launch; not in recorded or
-            // allocation-free calls)
+            // and the path is long enough to cover them (one launch of units
+            // at most, narrow or wide: the second stream's candidates hold
+            // one launch; not in recorded or allocation-free calls).  At one
+            // workgroup per CU the fused kernel takes about 2.1 times as long
+            // per event as at two, and the HBM-path kernels beside it about
+            // 1.4 times their time alone: the overlap saves time while the
+            // path's records are at least about 5/8 of the counted events.
             uint64_t big_recs = 0;
             for (const BigPhase &bp : big) big_recs += bp.count;
             overlap = FUSED_BESIDE && C.beside && ev[0] + ev[1] >= BESIDE_MIN && big_recs >= BESIDE_MIN &&
+                      big_recs * 8 >= (ev[0] + ev[1]) * 5 &&
                       qslot + 2 <= 64 && units[0].size() <= CAND_CAP && units[1].size() <= CAND_CAP &&
                       (units[0].empty() || units[1].empty());
             if (overlap && !ctx->side) {
