@@ -57,8 +57,8 @@ struct drf_ctx {
     hipEvent_t done = nullptr;
     hipEvent_t counted = nullptr;
     hipEvent_t parted = nullptr;        // a partition level's bucket starts are on the host
-    // the counted protocols' fused units beside the HBM path (created on
-    // first use): their stream, its start and its end
+    // the counted protocols' fused units beside the HBM path: their
+    // stream, its start and its end
     hipStream_t side = nullptr;
     hipEvent_t side_go = nullptr, side_done = nullptr;
     void *h_starts = nullptr;           // pinned host copy of those starts
@@ -1288,15 +1288,10 @@ int check_impl(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_off, con
             // path's records are at least about 5/8 of the counted events.
             uint64_t big_recs = 0;
             for (const BigPhase &bp : big) big_recs += bp.count;
-            overlap = FUSED_BESIDE && C.beside && ev[0] + ev[1] >= BESIDE_MIN && big_recs >= BESIDE_MIN &&
+            overlap = FUSED_BESIDE && C.beside && ctx->side && ev[0] + ev[1] >= BESIDE_MIN && big_recs >= BESIDE_MIN &&
                       big_recs * 8 >= (ev[0] + ev[1]) * 5 &&
                       qslot + 2 <= 64 && units[0].size() <= CAND_CAP && units[1].size() <= CAND_CAP &&
                       (units[0].empty() || units[1].empty());
-            if (overlap && !ctx->side) {
-                hipck(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-                hipck(hipEventCreateWithFlags(&ctx->side_go, hipEventDisableTiming));
-                hipck(hipEventCreateWithFlags(&ctx->side_done, hipEventDisableTiming));
-            }
             if (overlap) C.fill32(at<Best>(A, C.o_best2), 0xFFFFFFFFu, count * sizeof(Best));
             C.tr.mark("counted events", ev[0] + ev[1]);
             C.tr.mark("big-phase records", big_recs);
@@ -1474,12 +1469,16 @@ uint64_t scratch_estimate(const drf_ctx *tuned, std::vector<Plan> &&plans) {
     return C.needA + b;
 }
 
-// The context's synchronization events, created up front so that no
-// checking call creates any.
-bool ctx_events(drf_ctx *c) {
+// The context's synchronization events and (for contexts whose calls are
+// not recorded) its second stream, created up front so that no checking
+// call creates any.
+bool ctx_events(drf_ctx *c, bool side) {
     return hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&c->counted, hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&c->parted, hipEventDisableTiming) == hipSuccess;
+           hipEventCreateWithFlags(&c->parted, hipEventDisableTiming) == hipSuccess &&
+           (!side || (hipEventCreateWithFlags(&c->side_go, hipEventDisableTiming) == hipSuccess &&
+                      hipEventCreateWithFlags(&c->side_done, hipEventDisableTiming) == hipSuccess &&
+                      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess));
 }
 
 void fill_plan(const Plan &p, drf_plan *out) {
@@ -1576,7 +1575,7 @@ int drf_ctx_create(int hip_device, uint64_t scratch_limit_bytes, drf_ctx **out) 
     c->limit = scratch_limit_bytes;
     // the fixed scratch array's address on this device (looked up once per
     // device, with the device current) for allocation-free calls
-    if (!ctx_events(c) || fixed_scratch_address(hip_device, &c->fixed) != hipSuccess) {
+    if (!ctx_events(c, true) || fixed_scratch_address(hip_device, &c->fixed) != hipSuccess) {
         (void)hipGetLastError();
         drf_ctx_destroy(c);
         return DRF_E_HIP;
@@ -1733,7 +1732,7 @@ int drf_prepare_batch(drf_ctx *ctx, const uint32_t *code, const uint64_t *code_o
     p->priv->tune = ctx->tune;
     p->priv->cus = ctx->cus;
     p->rec.limit = ctx->limit;
-    if (!ctx_events(p->priv)) {
+    if (!ctx_events(p->priv, false)) {
         (void)hipGetLastError();
         drf_prepared_destroy(p);
         return DRF_E_HIP;
@@ -1839,7 +1838,7 @@ int drf_graph_create(drf_ctx *ctx, const drf_graph_caps *caps, void *stream, drf
         g->priv->limit = ctx->limit;
         g->priv->tune = ctx->tune;
         g->priv->cus = ctx->cus;
-        if (!ctx_events(g->priv)) throw Fail{DRF_E_HIP};
+        if (!ctx_events(g->priv, false)) throw Fail{DRF_E_HIP};
         hipck(hipEventCreateWithFlags(&g->staged, hipEventDisableTiming));
         // uploaded part first (one staging image), then the device-only part
         Bump b;
