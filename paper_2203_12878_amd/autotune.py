@@ -6,7 +6,9 @@ tunings by coordinate descent over
     digit_bits   (most index bits of one MSD partition level)
     unit_events  (events per fused unit)
     item_events  (events per count / emit work item)
-and keeps the fastest.  Results are cached per size class of the workload
+and keeps the fastest (a candidate replaces the best so far when it is at
+least 1% faster: the check-to-check spread of the large workloads is about
+0.5%).  Results are cached per size class of the workload
 (log2 of its planned access events, log2 of its protocol count, whether it
 has phases above one tile) in a JSON file; apply_cached() sets the cached
 tuning of a batch's size class on a Checker.  The package ships the cache
@@ -27,7 +29,7 @@ from . import drf
 SPACE = {
     "tile_events": [2048, 4096, 8192],
     "digit_bits": [6, 8, 10],
-    "unit_events": [4096, 16384, 32768, 65536, 262144],
+    "unit_events": [4096, 16384, 32768, 49152, 65536, 262144],
     "item_events": [1 << 14, 1 << 16, 1 << 18],
 }
 DEFAULT = {"tile_events": 8192, "digit_bits": 10, "unit_events": 1 << 15, "item_events": 1 << 16}
@@ -87,7 +89,7 @@ def tune(chk: "drf.Checker", batch: "drf.Batch", rounds: int = 2, reps: int = 2,
                 trials.append((cfg, t))
                 if verbose:
                     print("tune", cfg, "%.3f ms" % (t * 1e3), flush=True)
-                if t < best_t * 0.97:
+                if t < best_t * 0.99:
                     best, best_t, improved = cfg, t, True
         if not improved:
             break
