@@ -14,6 +14,8 @@ Prints one JSON line:
   parity against the stored oracle results;
 * `roofline`: the kernel class with the largest time, from HIP events the
   library records around its own launches on its own stream;
+* `paths` and `large` run with their own workloads' cached tunings (size
+  classes of the autotuner), the headline with its own;
 * `paths`: the batched path against the plain path (one drf_check_protocol
   per protocol) on the whole mixed and tree-reduction batches, both with
   parity;
@@ -273,11 +275,22 @@ def per_kernel(stats, steps):
             for k, v in stats.items() if v["launches"]}
 
 
-def compare_paths(drf, chk, name, steps):
+def leg_tuning(chk, batch, cache, base):
+    """The headline's tuning, then the cached tuning of the batch's size
+    class when there is one (cache None: the headline's)."""
+    from paper_2203_12878_amd import autotune
+    chk.set_tuning(**base)
+    ent = autotune.apply_cached(chk, batch, cache_path=cache) if cache else None
+    return dict(chk.tuning(), source="autotuner cache (%s)" % autotune.size_class(batch) if ent else "headline's")
+
+
+def compare_paths(drf, chk, name, steps, cache=None, base=None):
     """Batched (one check over the whole set) against plain (one protocol
-    per call) on a whole batched workload, both compared with the oracle."""
+    per call) on a whole batched workload, both compared with the oracle,
+    with the workload's own cached tuning."""
     items, wl, _ = workload(name, 0)
     batch = drf.Batch(items, 0)
+    tuning = leg_tuning(chk, batch, cache, base) if base else None
     out = {}
     for path, run, k in (("batched", chk.run_batch, steps), ("plain", chk.run_plain, 1)):
         secs, _ = timed(run, batch, k, 1)
@@ -289,7 +302,7 @@ def compare_paths(drf, chk, name, steps):
             "plain_records_per_s": round(recs / out["plain"][0], 1),
             "batched_ms": round(out["batched"][0] * 1e3, 3), "plain_ms": round(out["plain"][0] * 1e3, 3),
             "speedup": round(out["plain"][0] / out["batched"][0], 3),
-            "parity_batched": out["batched"][1], "parity_plain": out["plain"][1]}
+            "parity_batched": out["batched"][1], "parity_plain": out["plain"][1], "tuning": tuning}
 
 
 def serving(drf, rates):
@@ -449,9 +462,12 @@ def main():
         "kernels": per_kernel(stats, args.steps),
     }
     if not args.no_extras:
-        line["paths"] = {n: compare_paths(drf, chk, n, args.steps) for n in ("mixed", "tree")}
+        base = chk.tuning()
+        leg_cache = None if args.no_tuning_cache else cache
+        line["paths"] = {n: compare_paths(drf, chk, n, args.steps, leg_cache, base) for n in ("mixed", "tree")}
         litems, _, ldesc = workload("large", args.seed)
         lb = drf.Batch(litems, 0)
+        ltuning = leg_tuning(chk, lb, leg_cache, base)
         lsecs, lstats = timed(chk.run_plain, lb, max(3, args.steps), 1, lib, chk._ctx)
         lres = lb.collect()
         lrec = sum(r.num_records for r in lres)
@@ -461,7 +477,8 @@ def main():
                          "roofline": roofline(lstats, max(3, args.steps), lrec, "large"),
                          "effective_hbm_frac": round(lrec / lsecs * EFFECTIVE_BYTES_PER_RECORD /
                                                      (HBM_PEAK_GBS * 1e9), 4),
-                         "kernels": per_kernel(lstats, max(3, args.steps))}
+                         "kernels": per_kernel(lstats, max(3, args.steps)), "tuning": ltuning}
+        chk.set_tuning(**base)
         line["graph"] = graph_leg(drf, chk, args.steps)
         line["table_vs_partition"] = table_ab(drf, chk, min(args.steps, 5), lib)
         line["serving"] = serving(drf, [1000, 5000, 20000, 50000])

@@ -48,7 +48,8 @@ def test_graph_replays_match_oracle():
 
 @pytest.mark.parametrize("tune", [dict(tile_events=2048, digit_bits=6), dict(tile_events=4096, digit_bits=10),
                                   dict(tile_events=256, digit_bits=4, unit_events=256, item_events=1024),
-                                  dict(unit_events=49152, item_events=262144)])
+                                  dict(unit_events=49152, item_events=262144),
+                                  dict(unit_events=16384, item_events=262144), dict(digit_bits=8, unit_events=65536)])
 def test_tunings_keep_results_exact(tune):
     from paper_2203_12878_amd import drf
     items = _items()
